@@ -1,0 +1,326 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics -- none of them re-types the oracle's own formulas.
+
+* Gauss-Hermite rules: closed form of the 4-point rule, the Hermite moment
+  identities sum w x^(2k) = (2k-1)!!, and numpy's independent rule.
+* Equilibrium (Sec. II, Appendix A): the Maxwellian moment identities the
+  Hermite expansion must reproduce up to its order, and an independent
+  construction from the 1-D Hermite coefficients of a Gaussian.
+* Collision: moments conserved, equilibrium a fixed point.
+* Streaming: integer displacements reduce to an exact shift (np.roll); a
+  Fourier mode is multiplied by the closed-form overlap symbol.
+* Full step: exact conservation of mass, momentum and energy (the paper's
+  central claim, abstract and Sec. I), and the shear-wave decay rate against
+  the eigenvalue of an independently built linearised step operator; the
+  tau-dependence of the viscosity against the single-relaxation transport
+  coefficient of Sec. IV.
+* Walls (Sec. VII): mass balance and the rest-state fixed point.
+* Refined rows (Sec. III rectangular meshes): uniform-state invariance and
+  conservation.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e as He
+
+from paper_1004_5059_amd import inputs
+
+
+# ---------------------------------------------------------------- tables --
+def test_gauss_hermite_n4_closed_form(orc):
+    # 4-point rule: nodes +-sqrt(3 -+ sqrt 6), weights (3 +- sqrt 6)/12
+    x, w = orc.gauss_hermite(4)
+    s6 = math.sqrt(6.0)
+    xe = np.array([-math.sqrt(3 + s6), -math.sqrt(3 - s6), math.sqrt(3 - s6), math.sqrt(3 + s6)])
+    we = np.array([(3 - s6) / 12, (3 + s6) / 12, (3 + s6) / 12, (3 - s6) / 12])
+    np.testing.assert_allclose(x, xe, rtol=0, atol=2e-15)
+    np.testing.assert_allclose(w, we, rtol=2e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", [3, 4, 6, 8])
+def test_gauss_hermite_moments_and_numpy(orc, n):
+    x, w = orc.gauss_hermite(n)
+    for k in range(0, 2 * n):  # exact up to degree 2n-1
+        m = float(np.sum(w * x ** k))
+        exact = 0.0 if k % 2 else float(np.prod(np.arange(k - 1, 0, -2)) if k else 1.0)
+        assert abs(m - exact) <= 2e-14 * max(1.0, exact), (n, k, m, exact)
+    xn, wn = He.hermegauss(n)
+    np.testing.assert_allclose(x, xn, atol=1e-14)
+    np.testing.assert_allclose(w, wn / math.sqrt(2 * math.pi), rtol=1e-13)
+
+
+def test_lattice_shifts_euclid_and_component(orc):
+    lat = orc.OracleLattice(4, 3, cfl=0.9, cfl_norm=0)
+    smax = np.max(np.hypot(lat.s[:, 0], lat.s[:, 1]))
+    assert abs(smax - 0.9) < 1e-15
+    lat2 = orc.OracleLattice(4, 3, cfl=0.9, cfl_norm=1)
+    assert abs(np.max(np.abs(lat2.s)) - 0.9) < 1e-15
+    # 3-point rule {0, +-sqrt 3} with lambda = 1/sqrt 3 gives integer shifts
+    lat3 = orc.OracleLattice(3, 2, cfl=1.0, cfl_norm=1)
+    assert set(np.unique(lat3.s)) == {-1.0, 0.0, 1.0}
+
+
+# ----------------------------------------------------------- equilibrium --
+def _maxwell_hermite_coeff(p, u, T, nquad=60):
+    """E[He_p(X)] for X ~ N(u, T) by a high-order Gauss rule (numpy)."""
+    z, wz = He.hermegauss(nquad)
+    c = np.zeros(p + 1)
+    c[p] = 1.0
+    return float(np.sum(wz * He.hermeval(u + math.sqrt(T) * z, c)) / math.sqrt(2 * math.pi))
+
+
+def _feq_independent(lat, rho, ux, uy, T):
+    """Order-N truncation of the Maxwellian's expansion in tensor-product
+    Hermite polynomials: sum over p+q <= N of a_p(ux,T) a_q(uy,T)
+    He_p(xi_x) He_q(xi_y) / (p! q!)."""
+    out = np.zeros(lat.q)
+    for l in range(lat.q):
+        xa, xb = lat.xi[l]
+        acc = 0.0
+        for p in range(lat.order + 1):
+            for q in range(lat.order + 1 - p):
+                cp = np.zeros(p + 1); cp[p] = 1.0
+                cq = np.zeros(q + 1); cq[q] = 1.0
+                acc += (_maxwell_hermite_coeff(p, ux, T) * _maxwell_hermite_coeff(q, uy, T)
+                        * He.hermeval(xa, cp) * He.hermeval(xb, cq)
+                        / (math.factorial(p) * math.factorial(q)))
+        out[l] = lat.w[l] * rho * acc
+    return out
+
+
+@pytest.mark.parametrize("n,order", [(4, 2), (4, 3), (6, 3), (6, 4)])
+def test_feq_equals_independent_hermite_construction(orc, n, order):
+    lat = orc.OracleLattice(n, order)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        rho, ux, uy, T = 1 + 0.3 * rng.random(), 0.2 * rng.standard_normal(), \
+            0.2 * rng.standard_normal(), 1 + 0.2 * rng.standard_normal()
+        np.testing.assert_allclose(lat.feq(rho, ux, uy, T), _feq_independent(lat, rho, ux, uy, T),
+                                   rtol=1e-12, atol=1e-15)
+
+
+def _maxwell_moment(px, py, rho, ux, uy, T):
+    """E[X^px Y^py] rho for independent Gaussians (exact, via numpy rule)."""
+    z, wz = He.hermegauss(40)
+    mx = np.sum(wz * (ux + math.sqrt(T) * z) ** px) / math.sqrt(2 * math.pi)
+    my = np.sum(wz * (uy + math.sqrt(T) * z) ** py) / math.sqrt(2 * math.pi)
+    return rho * mx * my
+
+
+@pytest.mark.parametrize("n,order", [(4, 3), (6, 4)])
+def test_feq_reproduces_maxwellian_moments(orc, n, order):
+    """Moments of the truncated expansion equal the Maxwellian's up to total
+    degree `order` (quadrature degree 2n-1 >= order + order)."""
+    lat = orc.OracleLattice(n, order)
+    rho, ux, uy, T = 1.07, 0.05, -0.03, 1.1
+    f = lat.feq(rho, ux, uy, T)
+    for px in range(order + 1):
+        for py in range(order + 1 - px):
+            m = float(np.sum(f * lat.xi[:, 0] ** px * lat.xi[:, 1] ** py))
+            assert abs(m - _maxwell_moment(px, py, rho, ux, uy, T)) < 1e-13, (px, py)
+
+
+@pytest.mark.parametrize("n,order", [(3, 2), (4, 3), (6, 4)])
+def test_moments_of_equilibrium_recover_fields(orc, n, order):
+    lat = orc.OracleLattice(n, order)
+    for (rho, ux, uy, T) in [(1.0, 0.0, 0.0, 1.0), (0.9, 0.04, -0.02, 1.07), (1.2, -0.01, 0.03, 0.95)]:
+        r, vx, vy, t = lat.moments(lat.feq(rho, ux, uy, T))
+        assert abs(r - rho) < 1e-14 and abs(vx - ux) < 1e-14 and abs(vy - uy) < 1e-14
+        assert abs(t - T) < 1e-14
+        # energy form of Sec. II gives the same temperature
+        f = lat.feq(rho, ux, uy, T)
+        e = 0.5 * np.sum((lat.xi ** 2).sum(1) * f)
+        t_energy = (e - 0.5 * r * (vx * vx + vy * vy)) / r  # (D/2) rho T, D = 2
+        assert abs(t_energy - T) < 1e-14
+
+
+# -------------------------------------------------------------- collision --
+def test_collision_conserves_and_fixed_point(orc):
+    lat = orc.OracleLattice(4, 3)
+    g = orc.OracleGrid(lat, 8, 8, tau=0.7)
+    rng = np.random.default_rng(3)
+    rho, ux, uy, T = (1 + 0.02 * rng.standard_normal((8, 8)), 0.02 * rng.standard_normal((8, 8)),
+                      0.02 * rng.standard_normal((8, 8)), 1 + 0.02 * rng.standard_normal((8, 8)))
+    f_eq = g.set_fields(rho, ux, uy, T)
+    np.testing.assert_allclose(g.collide(f_eq), f_eq, rtol=0, atol=1e-15)
+    f = f_eq + inputs.population_noise(16, 8, 8, amp=1e-3, seed=5)
+    fs = g.collide(f)
+    np.testing.assert_allclose(g.fields(fs), g.fields(f), rtol=0, atol=2e-15)
+    assert not np.allclose(fs, f)
+
+
+# -------------------------------------------------------------- streaming --
+def test_integer_shift_is_exact_roll(orc):
+    lat = orc.OracleLattice(3, 2, cfl=1.0, cfl_norm=1)
+    g = orc.OracleGrid(lat, 11, 7, tau=1.0, collide=False)
+    f = np.random.default_rng(0).random(g.shape)
+    out = g.step(f)
+    for l in range(lat.q):
+        sx, sy = int(lat.s[l, 0]), int(lat.s[l, 1])
+        expect = np.roll(np.roll(f[l], sy, axis=0), sx, axis=1)
+        assert np.array_equal(out[l], expect), l
+
+
+@pytest.mark.parametrize("mx,my", [(1, 0), (0, 1), (3, 2), (5, -4)])
+def test_stream_fourier_symbol(orc, mx, my):
+    lat = orc.OracleLattice(4, 3)
+    nx, ny = 16, 12
+    g = orc.OracleGrid(lat, nx, ny, tau=1.0, collide=False)
+    kx, ky = 2 * np.pi * mx / nx, 2 * np.pi * my / ny
+    ph = kx * np.arange(nx)[None, :] + ky * np.arange(ny)[:, None]
+    fc = np.broadcast_to(np.cos(ph), g.shape).copy()
+    fs = np.broadcast_to(np.sin(ph), g.shape).copy()
+    oc, os_ = g.stream(fc), g.stream(fs)
+    for l in range(lat.q):
+        sym = 1.0 + 0j
+        for s, k in ((lat.s[l, 0], kx), (lat.s[l, 1], ky)):
+            sym *= (1 - abs(s)) + abs(s) * np.exp(-1j * k * np.sign(s))
+        expect = sym * np.exp(1j * ph)
+        np.testing.assert_allclose(oc[l] + 1j * os_[l], expect, atol=1e-14)
+
+
+def test_stream_preserves_population_sums_and_uniform(orc):
+    lat = orc.OracleLattice(6, 4)
+    g = orc.OracleGrid(lat, 9, 10, tau=1.0, collide=False)
+    f = np.random.default_rng(1).random(g.shape)
+    out = g.stream(f)
+    np.testing.assert_allclose(out.sum(axis=(1, 2)), f.sum(axis=(1, 2)), rtol=1e-14)
+    u = np.ones(g.shape) * lat.w[:, None, None]
+    np.testing.assert_allclose(g.stream(u), u, rtol=1e-15)
+
+
+# ------------------------------------------------------------- full step --
+def test_c0_conservation_200_steps(orc):
+    lat = orc.OracleLattice(4, 3)
+    g = orc.OracleGrid(lat, 64, 64, tau=0.8)
+    f0 = g.set_fields(*inputs.shear_wave_fields(64, 64), inputs.population_noise(16, 64, 64, seed=0))
+    t0 = g.totals(f0)
+    f = g.run(f0, 200)
+    t1 = g.totals(f)
+    scale_p = np.sum(np.abs(lat.xi[:, :, None, None] * f[:, None]), axis=(0, 2, 3))
+    assert abs(t1[0] - t0[0]) / t0[0] <= 1e-13
+    assert abs(t1[1] - t0[1]) / scale_p[0] <= 1e-13
+    assert abs(t1[2] - t0[2]) / scale_p[1] <= 1e-13
+    assert abs(t1[3] - t0[3]) / t0[3] <= 1e-13
+
+
+def _linear_step_matrix(lat, tau, kx, ky):
+    """M(k) = diag(S(k)) (I - (I - J)/tau) with J the linearisation of
+    f -> feq(moments(f)) about rho=1, u=0, T=1:
+      J_lm = w_l [1 + xi_l.xi_m + (c_l^2 - D)(c_m^2 - D)/(2D)]."""
+    Dm = 2.0
+    c2 = (lat.xi ** 2).sum(1)
+    J = lat.w[:, None] * (1 + lat.xi @ lat.xi.T + np.outer(c2 - Dm, c2 - Dm) / (2 * Dm))
+    S = np.ones(lat.q, dtype=complex)
+    for d, k in ((0, kx), (1, ky)):
+        s = lat.s[:, d]
+        S *= (1 - np.abs(s)) + np.abs(s) * np.exp(-1j * k * np.sign(s))
+    return np.diag(S) @ (np.eye(lat.q) - (np.eye(lat.q) - J) / tau)
+
+
+def _shear_eigenvalue(lat, tau, k):
+    M = _linear_step_matrix(lat, tau, 0.0, k)
+    ev, V = np.linalg.eig(M)
+    n = lat.n
+    refl = np.array([(n - 1 - l // n) * n + l % n for l in range(lat.q)])  # xi_x -> -xi_x
+    best = None
+    for i in range(lat.q):
+        v = V[:, i]
+        odd = np.linalg.norm(v + v[refl]) < 1e-6 * np.linalg.norm(v)
+        if odd and (best is None or abs(ev[i]) > abs(best)):
+            best = ev[i]
+    assert abs(best.imag) < 1e-12
+    return best.real
+
+
+def _shear_amplitude(g, f):
+    ux = g.fields(f)[1].mean(axis=1)
+    j = np.arange(g.ny)
+    return 2.0 / g.ny * float(np.sum(ux * np.sin(2 * np.pi * j / g.ny)))
+
+
+def test_shear_wave_decays_at_linear_eigenvalue(orc):
+    lat = orc.OracleLattice(4, 3)
+    ny = 64
+    lam = _shear_eigenvalue(lat, 0.8, 2 * np.pi / ny)
+    g = orc.OracleGrid(lat, 4, ny, tau=0.8)
+    f = g.set_fields(*inputs.shear_wave_fields(4, ny, eps=1e-3))
+    f100 = g.run(f, 100)
+    f200 = g.run(f100, 100)
+    ratio = _shear_amplitude(g, f200) / _shear_amplitude(g, f100)
+    assert abs(ratio - lam ** 100) < 1e-6 * lam ** 100
+
+
+def test_viscosity_difference_matches_transport_coefficient(orc):
+    """nu(tau1) - nu(tau2) = lambda^2 T (tau1 - tau2): the single-relaxation
+    shear viscosity eta = rho T tau of Sec. IV in lattice units; the upwind
+    part of the remap cancels in the difference."""
+    lat = orc.OracleLattice(4, 3)
+    ny = 64
+    k = 2 * np.pi / ny
+    nus = []
+    for tau in (0.8, 0.55):
+        g = orc.OracleGrid(lat, 4, ny, tau=tau)
+        f100 = g.run(g.set_fields(*inputs.shear_wave_fields(4, ny, eps=1e-3)), 100)
+        f300 = g.run(f100, 200)
+        nus.append(-math.log(_shear_amplitude(g, f300) / _shear_amplitude(g, f100)) / (200 * k * k))
+    assert abs((nus[0] - nus[1]) - lat.lam ** 2 * 0.25) < 2e-3 * lat.lam ** 2 * 0.25
+
+
+# ----------------------------------------------------------------- walls --
+def test_walls_rest_state_fixed_point(orc):
+    lat = orc.OracleLattice(4, 3)
+    for dy in (None, inputs.refined_wall_rows(h=16, band=3)):
+        ny = 16 if dy is None else len(dy)
+        g = orc.OracleGrid(lat, 6, ny, tau=0.7, dy=dy, walls=True, wall_lo=(0.0, 1.05),
+                           wall_hi=(0.0, 1.05))
+        f = g.set_fields(*inputs.uniform_fields(6, ny, rho=0.97, T=1.05))
+        np.testing.assert_allclose(g.run(f, 5), f, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("refined", [False, True])
+def test_walls_conserve_mass_and_balance_columns(orc, refined):
+    lat = orc.OracleLattice(4, 3)
+    dy = inputs.refined_wall_rows(h=24, band=4) if refined else None
+    ny = 24 if dy is None else len(dy)
+    g = orc.OracleGrid(lat, 10, ny, tau=0.7, dy=dy, walls=True, wall_lo=(0.0, 1.0),
+                       wall_hi=(0.05, 1.1))
+    f = g.set_fields(*inputs.shear_wave_fields(10, ny, eps=0.02),
+                     inputs.population_noise(16, ny, 10, amp=1e-3, seed=11))
+    m0 = g.totals(f)[0]
+    for _ in range(20):
+        fs = g.collide(f)
+        mlo, mhi = g.wall_incident(fs)
+        elo, ehi = g.wall_emitted(fs)
+        assert np.all(mlo > 0) and np.all(mhi > 0)
+        np.testing.assert_allclose(elo, mlo, rtol=1e-14)
+        np.testing.assert_allclose(ehi, mhi, rtol=1e-14)
+        f = g.stream(fs)
+    assert abs(g.totals(f)[0] - m0) / m0 < 1e-13
+
+
+def test_unit_row_heights_equal_uniform_grid(orc):
+    lat = orc.OracleLattice(4, 3)
+    g1 = orc.OracleGrid(lat, 8, 12, tau=0.7, walls=True, wall_hi=(0.03, 1.1))
+    g2 = orc.OracleGrid(lat, 8, 12, tau=0.7, walls=True, wall_hi=(0.03, 1.1), dy=np.ones(12))
+    f = g1.set_fields(*inputs.shear_wave_fields(8, 12), inputs.population_noise(16, 12, 8, seed=2))
+    assert np.array_equal(g1.run(f, 7), g2.run(f, 7))
+
+
+def test_refined_rows_conserve_mass_periodic_uniform_invariant(orc):
+    lat = orc.OracleLattice(6, 4)
+    dy = np.array([0.5, 0.5, 1.0, 1.0, 0.25, 0.25, 0.5, 1.0, 1.0, 0.5])
+    g = orc.OracleGrid(lat, 5, len(dy), tau=0.9, dy=dy)
+    u = g.set_fields(*inputs.uniform_fields(5, len(dy), rho=1.1, T=0.98))
+    np.testing.assert_allclose(g.run(u, 3), u, rtol=1e-13)
+    f = u + inputs.population_noise(36, len(dy), 5, amp=1e-4, seed=4)
+    t0 = g.totals(f)
+    t1 = g.totals(g.run(f, 10))
+    np.testing.assert_allclose(t1, t0, rtol=1e-13, atol=1e-13 * abs(t0[0]))
+
+
+def test_residual_definition(orc):
+    q = np.array([1.0, 2.0, 2.0])
+    qp = np.array([1.0, 2.0, 1.0])
+    assert abs(orc.residual(q, qp, 10) - 1.0 / (10 * 3.0)) < 1e-16
