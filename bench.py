@@ -1,0 +1,158 @@
+"""Throughput benchmark of the fused TVLBM step on one MI355X.
+
+Workload (the throughput configuration): 1024 x 1024 periodic grid, D2Q16
+(4-point Gauss-Hermite tensor set, 3rd-order equilibrium), FP32 populations
+in structure-of-arrays with compensated moment sums, tau = 0.6, initial
+rho = 1 + 0.01 * smoothed N(0,1), T = 1 + 0.05 sin(2 pi x / 1024), u = 0.
+One step = one pass of the fused collide + overlap-stream kernel over the
+whole grid.  D2Q36 (6-point set, 4th-order equilibrium) is run as a second
+line item.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline (D2Q16, 1024²); batched steady solves/s vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def _kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("tvlbm_kernels.hip", "tvlbm_core.h"):
+        h.update(open(os.path.join(ROOT, "paper_1004_5059_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.autotune import autotune
+    from paper_1004_5059_amd.tvlbm import Solver
+
+    s = Solver(size, size, n_gh=n, dtype="f32", tau=0.6, device="cuda:0")
+    s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
+    if variant < 0:
+        variant, tune = autotune(s, steps=20)
+    else:
+        s.set_variant(variant)
+        tune = {}
+    s.step(warmup)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(steps)
+    b.record(s.stream)
+    b.synchronize()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    _, tot = s.moments()
+    s.close()
+    q = n * n
+    cells = size * size
+    launch_s = ms / 1e3 / steps
+    bytes_per_launch = 8 * q * cells  # one FP32 read + one write per population
+    return {
+        "mlups": cells * steps / (ms / 1e3) / 1e6,
+        "ms_per_step": ms / steps,
+        "variant": variant,
+        "tune_ms": {str(k): round(v, 5) for k, v in tune.items()},
+        "achieved_gbs": bytes_per_launch / launch_s / 1e9,
+        "bytes_per_launch": bytes_per_launch,
+        "mass": float(tot[0]),
+    }
+
+
+def cpu_baseline(size: int, target_s: float = 12.0):
+    """The FP64 oracle, as it stands, on this host's cores: a bounded sample
+    (a few steps of the same 1024^2 D2Q16 workload)."""
+    from oracle import oracle as orc
+    from paper_1004_5059_amd import inputs
+
+    lat = orc.OracleLattice(4, 3)
+    g = orc.OracleGrid(lat, size, size, tau=0.6)
+    f = g.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
+    t = time.perf_counter()
+    f = g.run(f, 1)
+    one = time.perf_counter() - t
+    steps = max(1, min(50, int(target_s / max(one, 1e-3))))
+    t = time.perf_counter()
+    g.run(f, steps)
+    dt = time.perf_counter() - t
+    return {"value": size * size * steps / dt / 1e6, "unit": "MLUPS", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the {size}x{size} D2Q16 workload"}
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "fused_step_d2q16_1024_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != _kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-d2q36", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the TVLBM path here is single-GPU "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    r16 = run_lattice(4, args.size, args.steps, args.warmup, args.variant)
+    r36 = None if args.no_d2q36 else run_lattice(6, args.size, args.steps, args.warmup, args.variant)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.size)
+    achieved = r16["achieved_gbs"]
+    out = {
+        "metric": METRIC,
+        "value": round(r16["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r16["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D2Q16 {args.size}x{args.size} periodic, FP32 SoA, tau=0.6, "
+                               "smoothed-density init", "grid": [args.size, args.size],
+                   "lattice": "D2Q16", "eq_order": 3, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile()},
+        "cpu_baseline": cpu,
+        "variant": r16["variant"],
+        "d2q36": None if r36 is None else {
+            "mlups": round(r36["mlups"], 1), "ms_per_step": round(r36["ms_per_step"], 5),
+            "achieved_gbs": round(r36["achieved_gbs"], 1),
+            "frac": round(r36["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": r36["variant"]},
+        "autotune_ms_per_step": r16["tune_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * tvlbm.h -- C ABI of the MI355X (gfx950) TVLBM library.
+ *
+ * The library advances the thermal volumetric lattice Boltzmann model of
+ * Sbragaglia & Sugiyama ("Volumetric formulation of lattice Boltzmann models
+ * with energy conservation") on a rectangular grid:
+ *
+ *   one step = BGK collision toward the Hermite-expanded equilibrium in
+ *   (rho, u, T) (Sec. II, eq.(lb), Appendix A), then volumetric streaming:
+ *   every population's cell, displaced by s_l = lambda * xi_l cells, is split
+ *   over the (at most four) cells it covers in proportion to the exact
+ *   overlap area (the volumetric scheme the paper builds on, Sec. I), so mass,
+ *   momentum and energy are conserved with off-lattice Gauss-Hermite
+ *   velocities.  Optional diffuse walls in y follow eq.(IMPOSITION)
+ *   (Sec. VII); optional non-uniform row heights follow the rectangular
+ *   meshes of Sec. III.
+ *
+ * Conventions shared by every entry point
+ *   - All functions return TVLBM_OK (0) or a negative TVLBM_E* code;
+ *     tvlbm_strerror() names a code, tvlbm_last_error() gives detail.
+ *   - Device pointers are borrowed: the caller allocates and frees them and
+ *     keeps them alive for the life of the context.  The library owns its
+ *     context, host tables and small internal device buffers (reduction
+ *     partials, flags, residual snapshots).
+ *   - Work is enqueued on the stream given at init (NULL = default stream)
+ *     and is asynchronous, except for calls that return host values, which
+ *     synchronise that stream.  A context is not thread-safe.
+ *   - Velocity numbering: l = a*n + b, a = x node index, b = y node index,
+ *     both ascending; xi_l = (x_a, x_b), w_l = w_a w_b (tensor-product
+ *     Gauss-Hermite rule, probabilists' weight, sum w = 1).
+ *   - Population arrays are structure-of-arrays [q][ny][pitch], x fastest.
+ *   - Macroscopic fields are [ny][nx] arrays in the context's dtype.
+ *   - State after k steps: f^k, the post-stream, pre-collision populations
+ *     (a step is collide, then stream).  The two caller-provided buffers
+ *     f_a/f_b hold, internally, post-collision populations minus the lattice
+ *     weights (deviation storage); read results through the entry points
+ *     below, not from those buffers.
+ */
+#ifndef TVLBM_H
+#define TVLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TVLBM_OK 0
+#define TVLBM_EINVAL (-1)        /* bad argument                          */
+#define TVLBM_EHIP (-2)          /* a HIP runtime call failed             */
+#define TVLBM_ENOMEM (-3)        /* internal allocation failed            */
+#define TVLBM_ENONFINITE (-4)    /* rho <= 0, T <= 0 or a non-finite value */
+#define TVLBM_EUNSUPPORTED (-5)  /* lattice/order/dtype not built         */
+#define TVLBM_ENOTCONVERGED (-6) /* step limit reached before tolerance   */
+#define TVLBM_EIO (-7)           /* checkpoint file error                 */
+
+enum { TVLBM_F32 = 0, TVLBM_F64 = 1 };
+enum { TVLBM_CFL_EUCLID = 0, TVLBM_CFL_COMPONENT = 1 };
+enum { TVLBM_BC_PERIODIC = 0, TVLBM_BC_DIFFUSE_WALLS = 1 };
+
+typedef struct tvlbm_ctx tvlbm_ctx;
+
+typedef struct tvlbm_desc {
+  int32_t n_gh;        /* Gauss-Hermite points per axis: 3, 4 or 6 (q = n_gh^2)   */
+  int32_t eq_order;    /* Hermite order of the equilibrium: (3,2) (4,3) (6,4)     */
+  int32_t dtype;       /* TVLBM_F32 or TVLBM_F64 (storage and arithmetic)         */
+  int32_t nx, ny;      /* cells; nx >= 2, ny >= 2                                 */
+  int32_t cfl_norm;    /* TVLBM_CFL_EUCLID: cfl = lambda*max|xi_l| (2-norm);      */
+                       /* TVLBM_CFL_COMPONENT: cfl = lambda*max|x_a|              */
+  int64_t ld;          /* row pitch of f_a/f_b in elements (>= nx); 0 = nx        */
+                       /* rounded up to a multiple of 64                          */
+  double tau;          /* BGK relaxation time in steps, > 0.5                     */
+  double cfl;          /* largest displacement per step, in cells (<= 1 per axis) */
+  int32_t collide;     /* 1 normally; 0 = pure streaming                          */
+  int32_t y_bc;        /* TVLBM_BC_PERIODIC or TVLBM_BC_DIFFUSE_WALLS             */
+  int32_t compensated; /* F32 only: 1 = compensated moment sums, 0 = plain sums   */
+  int32_t reserved;    /* must be 0                                               */
+  double wall_lo_ux, wall_lo_T; /* wall at y = 0: x velocity, temperature         */
+  double wall_hi_ux, wall_hi_T; /* wall at y = H                                  */
+  const double *dy;    /* host, ny row heights in cells (x spacing is 1);         */
+                       /* NULL = unit rows.  Non-uniform rows need walls.          */
+  void *f_a, *f_b;     /* device, each q*ny*ld elements of dtype, caller-owned    */
+  void *stream;        /* hipStream_t, or NULL for the default stream             */
+} tvlbm_desc;
+
+/* Create a context: validates the descriptor, builds the Gauss-Hermite
+ * velocity set, displacements and overlap tables, allocates small internal
+ * device buffers.  Populations are undefined until tvlbm_set_fields or
+ * tvlbm_set_populations.  EINVAL / EUNSUPPORTED / EHIP / ENOMEM. */
+int tvlbm_init(const tvlbm_desc *desc, tvlbm_ctx **ctx);
+int tvlbm_destroy(tvlbm_ctx *ctx);
+
+/* f^0 = feq(rho, u, T) (Sec. II, Appendix A) + noise, and step counter 0.
+ * rho/ux/uy/T: device [ny][nx]; noise: device [q][ny][nx] or NULL. */
+int tvlbm_set_fields(tvlbm_ctx *ctx, const void *rho, const void *ux,
+                     const void *uy, const void *T, const void *noise);
+/* f^0 = f (device [q][ny][nx], absolute populations), step counter 0. */
+int tvlbm_set_populations(tvlbm_ctx *ctx, const void *f);
+
+/* Advance nsteps >= 0 steps (asynchronous). */
+int tvlbm_step(tvlbm_ctx *ctx, int32_t nsteps);
+
+/* f^k (absolute, pre-collision) into device [q][ny][nx]; asynchronous. */
+int tvlbm_populations(tvlbm_ctx *ctx, void *f_out);
+/* C(f^k), the post-collision populations, into device [q][ny][nx]. */
+int tvlbm_post_collision(tvlbm_ctx *ctx, void *g_out);
+
+/* Moments of f^k: rho, u, T (Sec. II, central form of T) into the device
+ * [ny][nx] arrays given (each may be NULL), and the FP64 totals
+ * M = sum f dA, P = sum xi f dA, E = 1/2 sum |xi|^2 f dA into totals[4]
+ * (host, may be NULL).  Synchronises.  ENONFINITE if any cell has rho <= 0,
+ * T <= 0 or a non-finite moment. */
+int tvlbm_moments(tvlbm_ctx *ctx, void *rho, void *ux, void *uy, void *T,
+                  double totals[4]);
+
+/* Residual r = ||q^k - q^m||_2 / ((k - m) ||q^k||_2), q = stacked
+ * (rho, ux, uy, T) over all cells, where m is the step of the previous call
+ * (r = +inf on the first call or if no step was taken).  Synchronises. */
+int tvlbm_residual(tvlbm_ctx *ctx, double *r);
+
+/* Run until the residual over k_interval steps is below tol, or max_steps.
+ * steps_done/r_final (host, may be NULL).  ENOTCONVERGED at the limit. */
+int tvlbm_solve(tvlbm_ctx *ctx, int64_t max_steps, double tol,
+                int32_t k_interval, int64_t *steps_done, double *r_final);
+
+/* Step counter k. */
+int tvlbm_step_count(const tvlbm_ctx *ctx, int64_t *k);
+
+/* Lattice tables (host arrays): xi[2q] (Hermite units), w[q],
+ * shift[2q] (cells per step, as used by the kernels), lambda. */
+int tvlbm_lattice(const tvlbm_ctx *ctx, double *xi, double *w, double *shift,
+                  double *lambda);
+
+/* Checkpoint: header + raw state; tvlbm_load needs an identical descriptor. */
+int tvlbm_save(tvlbm_ctx *ctx, const char *path);
+int tvlbm_load(tvlbm_ctx *ctx, const char *path);
+
+/* Launch-shape variant of the fused step kernel (rows per wavefront and
+ * waves per workgroup); all variants compute identical results.  0 = the
+ * default.  tvlbm_num_variants gives the count. */
+int tvlbm_num_variants(void);
+int tvlbm_set_variant(tvlbm_ctx *ctx, int32_t variant);
+
+const char *tvlbm_strerror(int code);
+const char *tvlbm_last_error(const tvlbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVLBM_H */

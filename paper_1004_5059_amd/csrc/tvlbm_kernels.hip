@@ -1,0 +1,484 @@
+// tvlbm_kernels.hip -- HIP kernels of the fused TVLBM step for gfx950.
+//
+// k_march: the fused step.  One lane owns one column of a strip and marches
+// down a segment of rows.  Stored state is the post-collision deviation
+// g^k; per row the lane
+//   1. pulls f^{k+1} = S(g^k) with the exact-overlap weights: per axis the
+//      shifted unit cell covers the same cell with weight 1-|s| and the
+//      upstream neighbour with weight |s| (at most four cells in 2-D); the
+//      x-pulled value of the previous row is kept in a register, so every
+//      population costs two loads (centre and upstream column) per cell;
+//   2. forms the moments (compensated sums in FP32), the Hermite equilibrium
+//      and the BGK update in registers;
+//   3. stores g^{k+1}, coalesced, structure-of-arrays.
+// Diffuse walls (Sec. VII, eq.(IMPOSITION)) enter as ghost values at the
+// first and last row: the mass carried through the wall by the incident
+// populations of the wall row is re-emitted into the outgoing populations
+// with the flux-weighted wall Maxwellian.
+//
+// Work distribution is XCD-aware: workgroups are dispatched round-robin over
+// the 8 XCDs, so the tile index is remapped to give each XCD a contiguous
+// band of tiles (neighbouring row segments share halo rows in that XCD's L2).
+#include "tvlbm_core.h"
+#include "tvlbm_launch.h"
+
+namespace tvlbm {
+
+__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// sign of node a of an N-point symmetric rule: -1, 0 (odd N middle), +1
+template <int N>
+__host__ __device__ constexpr int node_sign(int a) {
+  return (2 * a + 1 < N) ? -1 : ((2 * a + 1 > N) ? 1 : 0);
+}
+
+// Element load at the wave-uniform instance base plus a 32-bit element
+// offset (population plane + row + column; the host guarantees the whole
+// instance block is below 4 GiB), which maps to the SGPR-base + VGPR-offset
+// addressing mode of global loads and stores.
+template <typename R>
+__device__ __forceinline__ R ldo(const R* __restrict__ base, uint32_t e) {
+  return *(const R*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(R)));
+}
+template <typename R>
+__device__ __forceinline__ void sto(R* __restrict__ base, uint32_t e, R v) {
+  *(R*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(R))) = v;
+}
+
+// Lane offsets of one row: centre, left and right neighbour (periodic in x).
+struct RowOff {
+  uint32_t c, m, p;
+};
+__device__ __forceinline__ RowOff row_off(uint32_t rowbase, int ic, int im, int ip) {
+  return RowOff{rowbase + (uint32_t)ic, rowbase + (uint32_t)im, rowbase + (uint32_t)ip};
+}
+
+// x part of the overlap remap for node a: value landing in the centre
+// column from the centre (weight 1-p) and the upstream column (weight p).
+template <typename R, int N>
+__device__ __forceinline__ R xpull(const Lat<R>& L, const R* __restrict__ s, uint32_t lo, int a,
+                                   const RowOff& o) {
+  const int sg = node_sign<N>(a);
+  R vc = ldo(s, lo + o.c);
+  if (sg > 0) return fmaR(L.qm[a], vc, L.p[a] * ldo(s, lo + o.m));
+  if (sg < 0) return fmaR(L.qm[a], vc, L.p[a] * ldo(s, lo + o.p));
+  return vc;
+}
+
+// Deviation part of the mass (per unit column width) that the populations
+// moving in direction dir (-1 down, +1 up) carry out of one row through the
+// wall, landing in column c:  m(c) = sum_{b: sign(x_b)=dir} p_b sum_a X_a(d_ab)(c).
+// The rest-state part sum p_b w_b is folded into the host constants kap_*.
+template <typename R, int N>
+__device__ __forceinline__ R wall_mass(const Lat<R>& L, const R* __restrict__ s, int64_t plane,
+                                       uint32_t rowbase, int c, int nx, int dir) {
+  const RowOff o = row_off(rowbase, c, wrapc(c - 1, nx), wrapc(c + 1, nx));
+  R m = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    if (node_sign<N>(b) != dir) continue;
+    R acc = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) acc += xpull<R, N>(L, s, (uint32_t)((a * N + b) * plane), a, o);
+    m = fmaR(L.p[b], acc, m);
+  }
+  return m;
+}
+
+// x-pull of a ghost row whose value at column c is kap + phi * m(c)
+template <typename R, int N>
+__device__ __forceinline__ R ghost_pull(const Lat<R>& L, int a, R kap, R phi, R m_c, R m_m, R m_p) {
+  const int sg = node_sign<N>(a);
+  R mx = m_c;
+  if (sg > 0) mx = fmaR(L.qm[a], m_c, L.p[a] * m_m);
+  if (sg < 0) mx = fmaR(L.qm[a], m_c, L.p[a] * m_p);
+  return fmaR(phi, mx, kap);
+}
+
+// Everything one lane does for one row j: pull, moments, equilibrium,
+// collision, store (or the auxiliary outputs).  GHOST_HI: row j is the last
+// row of a walled channel and the downward populations pull the top ghost.
+template <typename R, int N, int ORD, bool COMP, int MODE, bool GHOST_HI>
+__device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& P,
+                                          const R* __restrict__ s, R (&hp)[N * N], int j,
+                                          int i, int ic, int im, int ip, bool active,
+                                          bool ident, double (&tot)[4], int& bad) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const int nx = P.nx, ny = P.ny;
+  const int64_t plane = P.plane;
+  const uint32_t rj = (uint32_t)j * (uint32_t)P.ld;
+  R d[Q];
+  if (ident) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) d[l] = ldo(s, (uint32_t)(l * plane) + rj + (uint32_t)ic);
+  } else {
+    const RowOff oj = row_off(rj, ic, im, ip);
+    const uint32_t rn = (j + 1 == ny) ? 0u : rj + (uint32_t)P.ld;
+    const RowOff on = row_off(rn, ic, im, ip);
+    R m_c = R(0), m_m = R(0), m_p = R(0);
+    if constexpr (GHOST_HI) {
+      m_c = wall_mass<R, N>(L, s, plane, rj, ic, nx, +1);
+      m_m = wall_mass<R, N>(L, s, plane, rj, im, nx, +1);
+      m_p = wall_mass<R, N>(L, s, plane, rj, ip, nx, +1);
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        const uint32_t pl = (uint32_t)(l * plane);
+        if (sg > 0) {  // moving up: rows j (1-p) and j-1 (p)
+          R hn = xpull<R, N>(L, s, pl, a, oj);
+          d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
+          hp[l] = hn;
+        } else if (sg < 0) {  // moving down: rows j (1-p) and j+1 (p)
+          R hn;
+          if constexpr (GHOST_HI)
+            hn = ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], m_c, m_m, m_p);
+          else
+            hn = xpull<R, N>(L, s, pl, a, on);
+          d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
+          hp[l] = hn;
+        } else {
+          d[l] = xpull<R, N>(L, s, pl, a, oj);
+        }
+      }
+    }
+  }
+
+  R drho, jx, jy, ed;
+  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<R> F = fields_from(drho, jx, jy, ed);
+
+  if constexpr (MODE != MODE_STEP) {
+    const bool want_fields = (MODE == MODE_CHECK) || (A.aux & AUX_FIELDS);
+    if (want_fields && active) {
+      const R T = R(1) + F.th;
+      if (!(F.rho > R(0)) || !(T > R(0)) || !__builtin_isfinite(F.ux + F.uy + F.rho + T)) bad = 1;
+      if (A.fields) {
+        R* fo = A.fields + P.fld + (int64_t)j * nx + i;
+        const int64_t fp = (int64_t)nx * ny;
+        fo[0] = F.rho;
+        fo[fp] = F.ux;
+        fo[2 * fp] = F.uy;
+        fo[3 * fp] = T;
+      }
+      double m = 0.0, px = 0.0, py = 0.0, e = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const double fa = L.wd[l] + (double)d[l];
+          m += fa;
+          px += L.xd[a] * fa;
+          py += L.xd[b] * fa;
+          e += 0.5 * (L.xd[a] * L.xd[a] + L.xd[b] * L.xd[b]) * fa;
+        }
+      }
+      tot[0] += m; tot[1] += px; tot[2] += py; tot[3] += e;
+    }
+  }
+
+  if constexpr (MODE == MODE_AUX) {
+    if (A.aux & AUX_POPS) {
+      if (active) {
+        const int64_t op = (int64_t)nx * ny;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) A.dst[l * op + (int64_t)j * nx + i] = d[l] + L.w[l];
+      }
+      return;
+    }
+    if (!(A.aux & AUX_POST)) return;
+  }
+
+  const EqCell<R> E = eq_cell<R, N>(L, F);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      const R Pl = eq_poly<R, N, ORD>(L, E, a, b);
+      const R g = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, Pl);
+      if (active) {
+        if constexpr (MODE == MODE_AUX) {
+          const int64_t op = (int64_t)nx * ny;
+          A.dst[l * op + (int64_t)j * nx + i] = g + L.w[l];
+        } else {
+          sto(A.dst + P.off, (uint32_t)(l * plane) + rj + (uint32_t)i, g);
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>& P, int i,
+                                           bool active, int j0, int j1, double (&tot)[4],
+                                           int& bad) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const int nx = P.nx, ny = P.ny;
+  const int64_t plane = P.plane;
+  const R* __restrict__ s = A.src + P.off;
+  const int ic = active ? i : 0;  // inactive lanes read a valid column, store nothing
+  const int im = ic == 0 ? nx - 1 : ic - 1;
+  const int ip = ic == nx - 1 ? 0 : ic + 1;
+  const bool ident = (MODE == MODE_AUX) && (A.aux & AUX_IDENTITY);
+
+  R hp[Q];
+  if (!ident) {
+    const bool ghost_lo = P.walls && j0 == 0;
+    R m_c = R(0), m_m = R(0), m_p = R(0);
+    if (ghost_lo) {
+      m_c = wall_mass<R, N>(L, s, plane, 0u, ic, nx, -1);
+      m_m = wall_mass<R, N>(L, s, plane, 0u, im, nx, -1);
+      m_p = wall_mass<R, N>(L, s, plane, 0u, ip, nx, -1);
+    }
+    const RowOff op = row_off((uint32_t)(j0 == 0 ? ny - 1 : j0 - 1) * (uint32_t)P.ld, ic, im, ip);
+    const RowOff oc = row_off((uint32_t)j0 * (uint32_t)P.ld, ic, im, ip);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        if (sg > 0) {
+          hp[l] = ghost_lo ? ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], m_c, m_m, m_p)
+                           : xpull<R, N>(L, s, (uint32_t)(l * plane), a, op);
+        } else if (sg < 0) {
+          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, oc);
+        } else {
+          hp[l] = R(0);
+        }
+      }
+    }
+  }
+
+  const int jmain = (P.walls && j1 == ny) ? j1 - 1 : j1;
+  for (int j = j0; j < jmain; ++j)
+    march_row<R, N, ORD, COMP, MODE, false>(A, P, s, hp, j, i, ic, im, ip, active, ident, tot, bad);
+  if (jmain < j1) {
+    if (ident)
+      march_row<R, N, ORD, COMP, MODE, false>(A, P, s, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
+    else
+      march_row<R, N, ORD, COMP, MODE, true>(A, P, s, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void block_totals(const double (&tot)[4], int bad, double* partials,
+                                             int32_t* flag) {
+  __shared__ double sh[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[4] = {tot[0], tot[1], tot[2], tot[3]};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] += __shfl_xor(v[c], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[wave][c] = v[c];
+  }
+  if (bad) flag[0] = 1;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    partials[(int64_t)blockIdx.x * 4 + c] = ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
+  }
+}
+
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = A.width;
+  const int spw = 64 / W;       // lane segments per wavefront
+  const int spb = 4 * spw;      // segments per workgroup
+  const int nb = gridDim.x;     // multiple of 8
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  int bad = 0;
+  if (t < A.n_tiles) {
+    const int tx = t % A.tiles_x, ty = t / A.tiles_x;
+    const int i = tx * W + (lane & (W - 1));
+    const int seg = ty * spb + wave * spw + lane / W;
+    const int j0 = seg * A.rows;
+    const int j1 = min(j0 + A.rows, A.inst.ny);
+    if (j0 < A.inst.ny)
+      march_lane<R, N, ORD, COMP, MODE>(A, A.inst, i, i < A.inst.nx, j0, j1, tot, bad);
+  }
+  if constexpr (MODE != MODE_STEP) {
+    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
+  }
+}
+
+// ----------------------------------------------------------------- init ---
+// f^0 (deviations) into `f0`, and g^0 = C(f^0) into `g0`, pitch ld.
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const Inst<R>& P = A.inst;
+  const int64_t n = (int64_t)P.nx * P.ny;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int j = (int)(c / P.nx), i = (int)(c % P.nx);
+  R d[Q];
+  if (A.fabs) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) d[l] = A.fabs[l * n + c] - L.w[l];
+  } else {
+    Fields<R> F;
+    F.rho = A.rho[c];
+    F.drho = F.rho - R(1);
+    F.ux = A.ux[c];
+    F.uy = A.uy[c];
+    F.th = A.T[c] - R(1);
+    const EqCell<R> E = eq_cell<R, N>(L, F);
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        d[l] = L.w[l] * fmaR(F.rho, eq_poly<R, N, ORD>(L, E, a, b), F.drho);
+        if (A.noise) d[l] += A.noise[l * n + c];
+      }
+  }
+  const int64_t o = P.off + (int64_t)j * P.ld + i;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) A.f0[o + l * P.plane] = d[l];
+  R drho, jx, jy, ed;
+  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<R> F = fields_from(drho, jx, jy, ed);
+  const EqCell<R> E = eq_cell<R, N>(L, F);
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      A.g0[o + l * P.plane] = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, eq_poly<R, N, ORD>(L, E, a, b));
+    }
+}
+
+// ------------------------------------------------------------ reductions --
+// out[c] = sum_b part[b*width + c], fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part, int nblk,
+                                                int width, double* __restrict__ out) {
+  __shared__ double sh[256];
+  for (int c = 0; c < width; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(int64_t)b * width + c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+    __syncthreads();
+  }
+}
+
+// per-block partial sums of (q - qp)^2 and q^2 over n values
+template <typename R>
+__global__ __launch_bounds__(256) void k_resid(const R* __restrict__ q, const R* __restrict__ qp,
+                                               int64_t n, double* __restrict__ part) {
+  __shared__ double sh[2][4];
+  double a = 0.0, b = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    const double v = (double)q[k], dv = v - (double)qp[k];
+    a += dv * dv;
+    b += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sh[0][wave] = a; sh[1][wave] = b; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int c = threadIdx.x;
+    part[(int64_t)blockIdx.x * 2 + c] = ((sh[c][0] + sh[c][1]) + sh[c][2]) + sh[c][3];
+  }
+}
+
+// ------------------------------------------------------------- dispatch ---
+template <typename R, int N, int ORD, bool COMP>
+static hipError_t march_mode(int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (mode) {
+    case MODE_STEP: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
+    case MODE_CHECK: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_AUX>), g, b, 0, st, A); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename R, bool COMP>
+static hipError_t march_lat(int n, int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  switch (n) {
+    case 3: return march_mode<R, 3, 2, COMP>(mode, A, nblocks, st);
+    case 4: return march_mode<R, 4, 3, COMP>(mode, A, nblocks, st);
+    case 6: return march_mode<R, 6, 4, COMP>(mode, A, nblocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
+                        hipStream_t st) {
+  return comp ? march_lat<float, true>(n, mode, A, nblocks, st)
+              : march_lat<float, false>(n, mode, A, nblocks, st);
+}
+hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
+                        hipStream_t st) {
+  (void)comp;
+  return march_lat<double, false>(n, mode, A, nblocks, st);
+}
+
+template <typename R, bool COMP>
+static hipError_t init_lat(int n, const InitArgs<R>& A, hipStream_t st) {
+  const int64_t cells = (int64_t)A.inst.nx * A.inst.ny;
+  dim3 g((unsigned)((cells + 255) / 256)), b(256);
+  switch (n) {
+    case 3: hipLaunchKernelGGL((k_init<R, 3, 2, COMP>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_init<R, 4, 3, COMP>), g, b, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((k_init<R, 6, 4, COMP>), g, b, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int n, bool comp, const InitArgs<float>& A, hipStream_t st) {
+  return comp ? init_lat<float, true>(n, A, st) : init_lat<float, false>(n, A, st);
+}
+hipError_t launch_init(int n, bool comp, const InitArgs<double>& A, hipStream_t st) {
+  (void)comp;
+  return init_lat<double, false>(n, A, st);
+}
+
+hipError_t launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, part, nblk, width, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t resid_impl(const R* q, const R* qp, int64_t n, double* part, int nblk,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_resid<R>, dim3(nblk), dim3(256), 0, st, q, qp, n, part);
+  return hipGetLastError();
+}
+hipError_t launch_resid(const float* q, const float* qp, int64_t n, double* part, int nblk,
+                        hipStream_t st) {
+  return resid_impl(q, qp, n, part, nblk, st);
+}
+hipError_t launch_resid(const double* q, const double* qp, int64_t n, double* part, int nblk,
+                        hipStream_t st) {
+  return resid_impl(q, qp, n, part, nblk, st);
+}
+
+}  // namespace tvlbm

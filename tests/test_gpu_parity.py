@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: relative infinity norm 1e-12 for FP64 and 1e-5 for FP32
+populations and fields, the bars of the fused-step contract; conservation
+to round-off (FP64 1e-13 after 200 steps; FP32 storage 1e-6 with FP64
+totals); exact integer shifts bitwise.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_common import c0_inputs, make_pair, rel_inf, to_np  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+from paper_1004_5059_amd import inputs  # noqa: E402
+from paper_1004_5059_amd import tvlbm  # noqa: E402
+
+
+def _compare_state(s, g, f_ref, tol):
+    f_gpu = to_np(s.populations())
+    assert rel_inf(f_gpu, f_ref) <= tol, ("populations", rel_inf(f_gpu, f_ref))
+    post = to_np(s.post_collision())
+    post_ref = g.collide(f_ref)
+    assert rel_inf(post, post_ref) <= tol, ("post-collision", rel_inf(post, post_ref))
+    fld, tot = s.moments()
+    fld = to_np(fld)
+    ref = g.fields(f_ref)
+    assert rel_inf(fld[0], ref[0]) <= tol
+    assert rel_inf(fld[3], ref[3]) <= tol
+    for c in (1, 2):
+        assert np.max(np.abs(fld[c] - ref[c])) / max(np.max(np.abs(ref[c])), 0.01) <= tol
+    return tot
+
+
+@pytest.mark.parametrize("dtype,comp,tol", [("f64", True, 1e-12), ("f32", True, 1e-5),
+                                            ("f32", False, 1e-5)])
+def test_c0_shear_wave_parity(dtype, comp, tol):
+    """64x64 periodic D2Q16, tau 0.8, 200 steps, shear wave + noise."""
+    s, g = make_pair(64, 64, n=4, dtype=dtype, tau=0.8, compensated=comp)
+    fields, noise = c0_inputs()
+    s.set_fields(*fields, noise)
+    f_ref = g.set_fields(*fields, noise)
+    t0_ref = g.totals(f_ref)
+    _compare_state(s, g, f_ref, tol)
+    s.step(200)
+    f_ref = g.run(f_ref, 200)
+    tot = _compare_state(s, g, f_ref, tol)
+    cons = 1e-13 if dtype == "f64" else 1e-6
+    assert abs(tot[0] - t0_ref[0]) / t0_ref[0] <= cons
+    assert abs(tot[3] - t0_ref[3]) / t0_ref[3] <= cons
+    scale = np.sum(np.abs(f_ref)) * 2.4
+    assert abs(tot[1] - t0_ref[1]) / scale <= cons and abs(tot[2] - t0_ref[2]) / scale <= cons
+    s.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_d2q36_ragged_parity(dtype, tol):
+    """D2Q36 (order 4) on 80x37 (ragged strips and row segments), 60 steps."""
+    nx, ny = 80, 37
+    s, g = make_pair(nx, ny, n=6, dtype=dtype, tau=0.6)
+    fields = inputs.smoothed_density_fields(nx, ny, std=0.01, t_amp=0.05, seed=3)
+    noise = inputs.population_noise(36, ny, nx, amp=1e-5, seed=9)
+    s.set_fields(*fields, noise)
+    f_ref = g.set_fields(*fields, noise)
+    s.step(60)
+    _compare_state(s, g, g.run(f_ref, 60), tol)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_integer_displacements_are_exact_shifts(dtype):
+    """3-point rule with lambda = 1/sqrt(3): displacements in {-1, 0, 1};
+    with collision off the step is np.roll of every population, bitwise."""
+    nx, ny = 70, 9
+    s, _ = make_pair(nx, ny, n=3, dtype=dtype, collide=False, cfl=1.0, cfl_norm=1)
+    _, w, shift, _ = s.lattice()
+    npdt = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(5)
+    # f = w + k 2^-20 with |k| small: f - w and (f - w) + w are exact
+    f0 = (w.astype(npdt)[:, None, None] +
+          (rng.integers(-64, 64, size=(9, ny, nx)) * 2.0 ** -20).astype(npdt)).astype(npdt)
+    s.set_populations(f0)
+    s.step(5)
+    out = s.populations().cpu().numpy()
+    for l in range(9):
+        sx, sy = int(shift[l, 0]), int(shift[l, 1])
+        expect = np.roll(np.roll(f0[l], 5 * sy, axis=0), 5 * sx, axis=1)
+        assert np.array_equal(out[l], expect), l
+    s.close()
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(4, "f64", 1e-12), (4, "f32", 1e-5), (6, "f64", 1e-12)])
+def test_diffuse_walls_parity(n, dtype, tol):
+    """Diffuse walls (bottom at rest T=1, top moving u=0.05, T=1.1), 100 steps."""
+    nx, ny = 48, 21
+    kw = dict(walls=True, wall_lo=(0.0, 1.0), wall_hi=(0.05, 1.1))
+    s, g = make_pair(nx, ny, n=n, dtype=dtype, tau=0.7, **kw)
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    noise = inputs.population_noise(n * n, ny, nx, amp=1e-4, seed=1)
+    s.set_fields(*fields, noise)
+    f_ref = g.set_fields(*fields, noise)
+    m0 = g.totals(f_ref)[0]
+    s.step(100)
+    tot = _compare_state(s, g, g.run(f_ref, 100), tol)
+    assert abs(tot[0] - m0) / m0 <= (1e-13 if dtype == "f64" else 1e-6)
+    s.close()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_launch_variants_bitwise_identical(walls):
+    nx, ny = 100, 70
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    noise = inputs.population_noise(16, ny, nx, amp=1e-4, seed=2)
+    outs = []
+    for v in range(tvlbm.tvlbm_num_variants()):
+        s, _ = make_pair(nx, ny, n=4, dtype="f32", tau=0.7, walls=walls,
+                         wall_hi=(0.03, 1.05), variant=v)
+        s.set_fields(*fields, noise)
+        s.step(25)
+        outs.append(s.populations().cpu().numpy())
+        s.close()
+    for v, o in enumerate(outs[1:], 1):
+        assert np.array_equal(o, outs[0]), v
+
+
+def test_run_to_run_deterministic():
+    res = []
+    for _ in range(2):
+        s, _ = make_pair(96, 64, n=4, dtype="f32", tau=0.6)
+        fields, noise = c0_inputs(96, 64)
+        s.set_fields(*fields, noise)
+        s.step(50)
+        res.append((s.populations().cpu().numpy(), s.moments()[1]))
+        s.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_c1_full_size_sampled_cells(n):
+    """1024x1024 periodic, FP32, tau 0.6, smoothed-density init, in the
+    benchmark's launch configuration; 20 steps.  Each sampled cell is
+    checked against the oracle run on a periodic window around it whose
+    half-width exceeds the 20-cell domain of dependence."""
+    N, K = 1024, 20
+    s, _ = make_pair(N, N, n=n, dtype="f32", tau=0.6)
+    fields = inputs.smoothed_density_fields(N, N, std=0.01, t_amp=0.05, seed=1)
+    s.set_fields(*fields)
+    _, tot0 = s.moments()
+    s.step(K)
+    f = s.populations().cpu().numpy()
+    _, tot1 = s.moments()
+    assert abs(tot1[0] - tot0[0]) / tot0[0] <= 1e-6
+    assert abs(tot1[3] - tot0[3]) / tot0[3] <= 1e-6
+    lat = orc.OracleLattice(n, tvlbm.LATTICE_ORDER[n])
+    h = K + 2
+    W = 2 * h + 1
+    g = orc.OracleGrid(lat, W, W, tau=0.6)
+    for (ci, cj) in [(0, 0), (1023, 511), (37, 1000), (512, 3), (700, 700)]:
+        ii = np.arange(ci - h, ci + h + 1) % N
+        jj = np.arange(cj - h, cj + h + 1) % N
+        win = [a[np.ix_(jj, ii)] for a in fields]
+        fr = g.run(g.set_fields(*win), K)
+        ref = fr[:, h, h]
+        got = f[:, cj, ci]
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(fr)) <= 1e-5, (ci, cj)
+    s.close()
+
+
+def test_nonfinite_state_is_reported():
+    s, _ = make_pair(32, 16, n=4, dtype="f32")
+    fields, noise = c0_inputs(32, 16)
+    f = np.zeros((16, 16, 32))
+    lat = orc.OracleLattice(4, 3)
+    for l in range(16):
+        f[l] = lat.w[l]
+    f[3, 5, 7] = np.nan
+    s.set_populations(f)
+    s.step(2)
+    with pytest.raises(tvlbm.TvlbmError) as e:
+        s.moments()
+    assert e.value.code == tvlbm.TVLBM_ENONFINITE
+    s.close()
+
+
+def test_checkpoint_resume_bitwise(tmp_path):
+    fields, noise = c0_inputs(64, 32)
+    s, _ = make_pair(64, 32, n=4, dtype="f32", tau=0.7, walls=True, wall_hi=(0.05, 1.1))
+    s.set_fields(*fields, noise)
+    s.step(10)
+    p = str(tmp_path / "ck.bin")
+    tvlbm.tvlbm_save(s.ctx, p)
+    s.step(10)
+    a = s.populations().cpu().numpy()
+    tvlbm.tvlbm_load(s.ctx, p)
+    assert s.step_count == 10
+    s.step(10)
+    b = s.populations().cpu().numpy()
+    assert np.array_equal(a, b)
+    s.close()
+
+
+def test_residual_matches_field_definition():
+    nx, ny = 32, 24
+    s, _ = make_pair(nx, ny, n=4, dtype="f64", tau=0.8, walls=True, wall_hi=(0.04, 1.05))
+    s.set_fields(*inputs.uniform_fields(nx, ny))
+    r0 = s.residual()
+    assert r0 == float("inf")
+    q0 = to_np(s.moments()[0])
+    s.step(40)
+    q1 = to_np(s.moments()[0])
+    r = s.residual()
+    expect = orc.residual(q1, q0, 40)
+    assert abs(r - expect) <= 1e-10 * expect
+    s.close()
