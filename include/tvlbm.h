@@ -144,6 +144,60 @@ int tvlbm_set_variant(tvlbm_ctx *ctx, int32_t variant);
 const char *tvlbm_strerror(int code);
 const char *tvlbm_last_error(const tvlbm_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched steady solves: many independent channels (diffuse walls in y,
+ * periodic in x, uniform rows) of different sizes, relaxation times and wall
+ * states advanced together.  One persistent grid-stride kernel walks a
+ * device-resident work list of (instance, column strip, row segments); every
+ * k_interval steps a per-instance residual (same definition as
+ * tvlbm_residual) retires the instances below tol and the work list is
+ * compacted on the device.  A chunk of k_interval steps plus the residual and
+ * compaction is captured once as a HIP graph and replayed; the host reads one
+ * counter per replay.
+ * ------------------------------------------------------------------------ */
+typedef struct tvlbm_batch tvlbm_batch;
+
+typedef struct tvlbm_inst {
+  int32_t nx, ny;               /* cells                                     */
+  double tau;                   /* relaxation time in steps, > 0.5           */
+  double wall_lo_ux, wall_lo_T; /* wall at y = 0                             */
+  double wall_hi_ux, wall_hi_T; /* wall at y = H                             */
+} tvlbm_inst;
+
+typedef struct tvlbm_batch_desc {
+  int32_t n_gh, eq_order, dtype, compensated; /* as in tvlbm_desc            */
+  double cfl;
+  int32_t cfl_norm;
+  int32_t n_inst;
+  const tvlbm_inst *inst;       /* host, n_inst entries                      */
+  void *arena_a, *arena_b;      /* device, tvlbm_batch_sizes() pop elements  */
+  void *stream;                 /* hipStream_t; must not be the null stream  */
+} tvlbm_batch_desc;
+
+/* Element counts of one population arena (pop_elems) and of one packed
+ * field array (field_elems = sum over instances of 4*nx*ny; instance b's
+ * fields [4][ny][nx] = rho, ux, uy, T follow those of instance b-1). */
+int tvlbm_batch_sizes(const tvlbm_batch_desc *desc, int64_t *pop_elems,
+                      int64_t *field_elems);
+int tvlbm_batch_init(const tvlbm_batch_desc *desc, tvlbm_batch **b);
+int tvlbm_batch_destroy(tvlbm_batch *b);
+/* f^0 = feq(fields) per instance; fields: device, packed as above. */
+int tvlbm_batch_set_fields(tvlbm_batch *b, const void *fields);
+/* Run every instance until its residual over k_interval (even, >= 2) steps
+ * is below tol or it has taken max_steps.  steps_out (host, n_inst) gets the
+ * steps each instance took, r_out (host, n_inst, may be NULL) its last
+ * residual.  Synchronises.  ENOTCONVERGED if any instance hit max_steps. */
+int tvlbm_batch_run(tvlbm_batch *b, int64_t max_steps, double tol,
+                    int32_t k_interval, int64_t *steps_out, double *r_out);
+/* Fields of every instance's current state into fields_out (device, packed);
+ * synchronises; ENONFINITE as tvlbm_moments. */
+int tvlbm_batch_fields(tvlbm_batch *b, void *fields_out);
+/* Launch shape for instances with nx <= max_nx (size class): wavefront strip
+ * width (16, 32 or 64 columns) and rows per lane segment.  Results do not
+ * depend on the shape. */
+int tvlbm_batch_set_shape(tvlbm_batch *b, int32_t max_nx, int32_t width,
+                          int32_t rows);
+
 #ifdef __cplusplus
 }
 #endif

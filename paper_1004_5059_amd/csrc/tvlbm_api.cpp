@@ -36,6 +36,15 @@ struct Geometry {
   int tiles_x, n_tiles, nblocks;
 };
 
+// Non-uniform-row kernel: 64 columns x 4 rows per workgroup.
+Geometry geometry_rows(int nx, int ny) {
+  Geometry g;
+  g.tiles_x = (int)ceil_div(nx, 64);
+  g.n_tiles = (int)(g.tiles_x * ceil_div(ny, 4));
+  g.nblocks = (int)(ceil_div(g.n_tiles, 8) * 8);
+  return g;
+}
+
 Geometry geometry(int nx, int ny, const Variant& v) {
   Geometry g;
   const int spb = 4 * (64 / v.width);
@@ -71,8 +80,119 @@ struct tvlbm_ctx {
   Lat<double> latd{};
   Inst<float> instf{};
   Inst<double> instd{};
+  // non-uniform rows
+  bool rows = false;
+  void* d_taps = nullptr;
+  void* d_inc = nullptr;
+  double* d_dy = nullptr;
+  int32_t* d_rowflag = nullptr;
+  std::vector<double> dyh;
   std::string err;
 };
+
+namespace {
+
+double ovl(double a0, double a1, double b0, double b1) {
+  const double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+  return hi > lo ? hi - lo : 0.0;
+}
+
+struct TapD {
+  int src[3];
+  double w[3];
+  double glo, ghi;
+};
+struct IncD {
+  int j[4];
+  double len[4];
+};
+
+// Overlap tables of the remap on rows of heights dy (x spacing 1): the
+// shifted source interval [y_j + s, y_{j+1} + s] against target row k, with
+// periodic images when there are no walls, the wall-emission intervals
+// [0, s] (bottom, s > 0) and [H - |s|, H] (top, s < 0), and the lengths of
+// shifted rows lying beyond a wall.  Returns false if a target row needs more
+// than three source rows or more than four rows cross a wall.
+bool build_row_tables(const HostLattice& H, int ny, const double* dy, bool walls,
+                      std::vector<TapD>& taps, std::vector<IncD>& inc, std::vector<int32_t>& flag) {
+  const int n = H.n;
+  std::vector<double> y(ny + 1, 0.0);
+  for (int j = 0; j < ny; ++j) y[j + 1] = y[j] + dy[j];
+  const double Hy = y[ny];
+  taps.assign((size_t)n * ny, TapD{});
+  inc.assign(n, IncD{});
+  flag.assign(ny, 0);
+  for (int b = 0; b < n; ++b) {
+    const double s = (H.x[b] < 0 ? -1.0 : 1.0) * H.p[b];
+    for (int k = 0; k < ny; ++k) {
+      TapD& T = taps[(size_t)b * ny + k];
+      int cnt = 0;
+      for (int j = 0; j < ny; ++j) {
+        const double a0 = (y[j] - y[k]) + s, a1 = (y[j + 1] - y[k]) + s;
+        double len = ovl(a0, a1, 0.0, dy[k]);
+        if (!walls) len += ovl(a0 - Hy, a1 - Hy, 0.0, dy[k]) + ovl(a0 + Hy, a1 + Hy, 0.0, dy[k]);
+        if (len > 0.0) {
+          if (cnt == 3) return false;
+          T.src[cnt] = j;
+          T.w[cnt] = len / dy[k];
+          ++cnt;
+        }
+      }
+      for (int t = cnt; t < 3; ++t) { T.src[t] = k; T.w[t] = 0.0; }
+      T.glo = T.ghi = 0.0;
+      if (walls) {
+        if (s > 0.0) T.glo = ovl(-y[k], s - y[k], 0.0, dy[k]) / dy[k];
+        if (s < 0.0) T.ghi = ovl((Hy - y[k]) + s, Hy - y[k], 0.0, dy[k]) / dy[k];
+        if (T.glo > 0.0) flag[k] |= 1;
+        if (T.ghi > 0.0) flag[k] |= 2;
+      }
+    }
+    if (walls) {
+      IncD& I = inc[b];
+      int cnt = 0;
+      for (int j = 0; j < ny; ++j) {
+        const double len = s < 0.0 ? ovl(y[j] + s, y[j + 1] + s, -1e300, 0.0)
+                                   : ovl((y[j] - Hy) + s, (y[j + 1] - Hy) + s, 0.0, 1e300);
+        if (len > 0.0) {
+          if (cnt == 4) return false;
+          I.j[cnt] = j;
+          I.len[cnt] = len;
+          ++cnt;
+        }
+      }
+      for (int t = cnt; t < 4; ++t) { I.j[t] = 0; I.len[t] = 0.0; }
+    }
+  }
+  return true;
+}
+
+template <typename R>
+int upload_rows(tvlbm_ctx* c, const std::vector<TapD>& taps, const std::vector<IncD>& inc,
+                const std::vector<int32_t>& flag) {
+  std::vector<RowTap<R>> t(taps.size());
+  for (size_t k = 0; k < taps.size(); ++k) {
+    std::memset(&t[k], 0, sizeof t[k]);
+    for (int q = 0; q < 3; ++q) { t[k].src[q] = taps[k].src[q]; t[k].w[q] = (R)taps[k].w[q]; }
+    t[k].glo = (R)taps[k].glo;
+    t[k].ghi = (R)taps[k].ghi;
+  }
+  std::vector<IncRows<R>> in(inc.size());
+  for (size_t b = 0; b < inc.size(); ++b)
+    for (int q = 0; q < 4; ++q) { in[b].j[q] = inc[b].j[q]; in[b].len[q] = (R)inc[b].len[q]; }
+  if (hipMalloc(&c->d_taps, sizeof(RowTap<R>) * t.size()) != hipSuccess ||
+      hipMalloc(&c->d_inc, sizeof(IncRows<R>) * in.size()) != hipSuccess ||
+      hipMalloc(&c->d_dy, sizeof(double) * c->dyh.size()) != hipSuccess ||
+      hipMalloc(&c->d_rowflag, sizeof(int32_t) * flag.size()) != hipSuccess)
+    return TVLBM_ENOMEM;
+  if (hipMemcpy(c->d_taps, t.data(), sizeof(RowTap<R>) * t.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_inc, in.data(), sizeof(IncRows<R>) * in.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_dy, c->dyh.data(), sizeof(double) * c->dyh.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_rowflag, flag.data(), sizeof(int32_t) * flag.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return TVLBM_EHIP;
+  return TVLBM_OK;
+}
+
+}  // namespace
 
 static int fail(tvlbm_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -184,7 +304,7 @@ template <typename R>
 static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
                      bool want_totals) {
   const Variant v = kVariants[c->variant];
-  const Geometry g = geometry(c->d.nx, c->d.ny, v);
+  const Geometry g = c->rows ? geometry_rows(c->d.nx, c->d.ny) : geometry(c->d.nx, c->d.ny, v);
   MarchArgs<R> A;
   std::memset(&A, 0, sizeof A);
   A.lat = lat_of<R>(c);
@@ -199,6 +319,12 @@ static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst
   A.fields = (R*)fields;
   A.partials = c->d_part;
   A.flag = c->d_flag;
+  if (c->rows) {
+    A.taps = (const RowTap<R>*)c->d_taps;
+    A.inc = (const IncRows<R>*)c->d_inc;
+    A.dy = c->d_dy;
+    A.rowflag = c->d_rowflag;
+  }
   if (want_totals && g.nblocks > c->part_cap) return fail(c, TVLBM_EINVAL, "partials too small");
   HIPCHK(c, launch_march(c->hl.n, c->comp, mode, A, g.nblocks, c->st));
   if (want_totals) HIPCHK(c, launch_reduce(c->d_part, g.nblocks, 4, c->d_tot, c->st));
@@ -255,12 +381,14 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
   if (d->collide && !(d->tau > 0.5)) return bad(TVLBM_EINVAL, "tau");
   if (!d->f_a || !d->f_b || d->f_a == d->f_b) return bad(TVLBM_EINVAL, "buffers");
   if (d->reserved != 0) return bad(TVLBM_EINVAL, "reserved");
-  if (d->dy) {
-    for (int j = 0; j < d->ny; ++j)
-      if (d->dy[j] != 1.0) return bad(TVLBM_EUNSUPPORTED, "non-uniform rows");
-  }
   c->d = *d;
   c->d.dy = nullptr;
+  if (d->dy) {
+    for (int j = 0; j < d->ny; ++j)
+      if (!(d->dy[j] > 0.0) || !std::isfinite(d->dy[j])) return bad(TVLBM_EINVAL, "dy");
+    c->dyh.assign(d->dy, d->dy + d->ny);
+    c->rows = true;
+  }
   if (!build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &c->hl))
     return bad(TVLBM_EUNSUPPORTED, "lattice");
   c->f64 = d->dtype == TVLBM_F64;
@@ -268,6 +396,8 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
   c->ld = d->ld ? d->ld : ceil_div(d->nx, 64) * 64;
   if (c->ld < d->nx) return bad(TVLBM_EINVAL, "ld");
   c->plane = (int64_t)d->ny * c->ld;
+  if ((double)c->hl.q * (double)c->plane * (d->dtype == TVLBM_F64 ? 8.0 : 4.0) >= 4294967296.0)
+    return bad(TVLBM_EUNSUPPORTED, "population block of 4 GiB or more");
   c->st = (hipStream_t)d->stream;
   c->buf[0] = d->f_a;
   c->buf[1] = d->f_b;
@@ -280,6 +410,7 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
             d->wall_hi_T, d->nx, d->ny, c->ld, 0, 0, c->instd);
   int cap = 1024;  // also covers the residual reduction (<= 1024 blocks)
   for (int v = 0; v < kNumVariants; ++v) cap = std::max(cap, geometry(d->nx, d->ny, kVariants[v]).nblocks);
+  cap = std::max(cap, geometry_rows(d->nx, d->ny).nblocks);
   c->part_cap = cap;
   const size_t fbytes = (size_t)4 * d->nx * d->ny * esize(c);
   if (hipMalloc(&c->d_part, sizeof(double) * 4 * (size_t)cap) != hipSuccess ||
@@ -294,6 +425,20 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
     tvlbm_destroy(c);
     return TVLBM_EHIP;
   }
+  if (c->rows) {
+    std::vector<TapD> taps;
+    std::vector<IncD> inc;
+    std::vector<int32_t> flag;
+    if (!build_row_tables(c->hl, d->ny, c->dyh.data(), walls != 0, taps, inc, flag)) {
+      tvlbm_destroy(c);
+      return TVLBM_EUNSUPPORTED;
+    }
+    const int rc = c->f64 ? upload_rows<double>(c, taps, inc, flag) : upload_rows<float>(c, taps, inc, flag);
+    if (rc != TVLBM_OK) {
+      tvlbm_destroy(c);
+      return rc;
+    }
+  }
   *out = c;
   return TVLBM_OK;
 }
@@ -306,6 +451,10 @@ int tvlbm_destroy(tvlbm_ctx* c) {
   hipFree(c->d_flag);
   hipFree(c->d_fld[0]);
   hipFree(c->d_fld[1]);
+  hipFree(c->d_taps);
+  hipFree(c->d_inc);
+  hipFree(c->d_dy);
+  hipFree(c->d_rowflag);
   delete c;
   return TVLBM_OK;
 }
@@ -547,6 +696,410 @@ int tvlbm_load(tvlbm_ctx* c, const char* path) {
   c->step = h.step;
   c->initialised = true;
   c->fld_valid = false;
+  return TVLBM_OK;
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// Batched steady solves
+// ==========================================================================
+struct tvlbm_batch {
+  tvlbm_batch_desc d{};
+  std::vector<tvlbm_inst> inst;
+  HostLattice hl;
+  bool f64 = false, comp = true;
+  hipStream_t st = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  std::vector<int64_t> off, fld;
+  std::vector<int32_t> ld;
+  int64_t pop_elems = 0, field_elems = 0;
+  void* d_insts = nullptr;
+  Work* d_all = nullptr;
+  Work* d_work = nullptr;
+  int32_t* d_item_start = nullptr;
+  int32_t* d_dst_off = nullptr;
+  int32_t* d_nwork = nullptr;
+  int32_t* d_ntotal = nullptr;
+  int32_t* d_remaining = nullptr;
+  int32_t* d_active = nullptr;
+  int32_t* d_have_prev = nullptr;
+  int64_t* d_steps = nullptr;
+  double* d_resid = nullptr;
+  int32_t* d_flag = nullptr;
+  void* d_fields = nullptr;
+  void* d_prev = nullptr;
+  int32_t* h_remaining = nullptr;  // pinned
+  struct Shape { int max_nx, width, rows; };
+  std::vector<Shape> shapes;
+  int n_items = 0;
+  int items_cap = 0;
+  bool initialised = false;
+  bool stepped = false;
+  hipGraphExec_t gexec = nullptr;
+  int g_K = 0;
+  double g_tol = 0.0;
+  int64_t g_max = 0;
+  Lat<float> latf{};
+  Lat<double> latd{};
+  std::string err;
+};
+
+namespace {
+
+int bfail(tvlbm_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+#define BHIP(b, expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bfail((b), TVLBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+int64_t align64(int64_t v) { return (v + 63) / 64 * 64; }
+
+bool batch_layout(const tvlbm_batch_desc* d, int q, std::vector<int64_t>& off,
+                  std::vector<int64_t>& fld, std::vector<int32_t>& ld, int64_t& pop,
+                  int64_t& field) {
+  off.assign(d->n_inst, 0);
+  fld.assign(d->n_inst, 0);
+  ld.assign(d->n_inst, 0);
+  pop = 0;
+  field = 0;
+  const double esz = d->dtype == TVLBM_F64 ? 8.0 : 4.0;
+  for (int b = 0; b < d->n_inst; ++b) {
+    const tvlbm_inst& I = d->inst[b];
+    if (I.nx < 2 || I.ny < 2) return false;
+    ld[b] = (int32_t)((I.nx + 15) / 16 * 16);
+    off[b] = pop;
+    const int64_t block = (int64_t)q * I.ny * ld[b];
+    if ((double)block * esz >= 4294967296.0) return false;
+    pop = align64(pop + block);
+    fld[b] = field;
+    field += (int64_t)4 * I.nx * I.ny;
+  }
+  return true;
+}
+
+const tvlbm_batch::Shape& shape_for(const tvlbm_batch* b, int nx) {
+  for (const auto& s : b->shapes)
+    if (nx <= s.max_nx) return s;
+  return b->shapes.back();
+}
+
+int build_items(tvlbm_batch* b) {
+  std::vector<Work> all;
+  std::vector<int32_t> start(b->inst.size() + 1, 0);
+  for (size_t k = 0; k < b->inst.size(); ++k) {
+    start[k] = (int32_t)all.size();
+    const tvlbm_inst& I = b->inst[k];
+    const auto& S = shape_for(b, I.nx);
+    const int spw = 64 / S.width;
+    const int nseg = (I.ny + S.rows - 1) / S.rows;
+    for (int x0 = 0; x0 < I.nx; x0 += S.width)
+      for (int sg = 0; sg < nseg; sg += spw)
+        all.push_back(Work{(int32_t)k, x0, sg, S.width | (S.rows << 8)});
+  }
+  start[b->inst.size()] = (int32_t)all.size();
+  b->n_items = (int)all.size();
+  if (b->n_items > b->items_cap) {
+    hipFree(b->d_all);
+    hipFree(b->d_work);
+    b->d_all = b->d_work = nullptr;
+    BHIP(b, hipMalloc(&b->d_all, sizeof(Work) * all.size()));
+    BHIP(b, hipMalloc(&b->d_work, sizeof(Work) * all.size()));
+    b->items_cap = b->n_items;
+  }
+  BHIP(b, hipMemcpy(b->d_all, all.data(), sizeof(Work) * all.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_item_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_ntotal, &b->n_items, sizeof(int32_t), hipMemcpyHostToDevice));
+  if (b->gexec) {
+    hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return TVLBM_OK;
+}
+
+int batch_blocks(const tvlbm_batch* b) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->n_items, 4), 2048));
+}
+
+template <typename R>
+int batch_march(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
+                const Work* work) {
+  MarchArgs<R> A;
+  std::memset(&A, 0, sizeof A);
+  A.lat = std::is_same<R, float>::value ? *(Lat<R>*)(void*)&b->latf : *(Lat<R>*)(void*)&b->latd;
+  A.insts = (const Inst<R>*)b->d_insts;
+  A.work = work;
+  A.n_work = nwork;
+  A.aux = aux;
+  A.src = (const R*)src;
+  A.dst = (R*)dst;
+  A.fields = (R*)b->d_fields;
+  A.flag = b->d_flag;
+  BHIP(b, launch_march_batch(b->hl.n, b->comp, mode, A, batch_blocks(b), b->st));
+  return TVLBM_OK;
+}
+
+int bmarch(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
+           const Work* work) {
+  return b->f64 ? batch_march<double>(b, mode, aux, src, dst, nwork, work)
+                : batch_march<float>(b, mode, aux, src, dst, nwork, work);
+}
+
+template <typename R>
+int batch_resid(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
+  BatchCtl<R> C;
+  std::memset(&C, 0, sizeof C);
+  C.insts = (const Inst<R>*)b->d_insts;
+  C.fields = (const R*)b->d_fields;
+  C.prev = (R*)b->d_prev;
+  C.active = b->d_active;
+  C.have_prev = b->d_have_prev;
+  C.steps = b->d_steps;
+  C.resid = b->d_resid;
+  C.flag = b->d_flag;
+  C.K = K;
+  C.tol = tol;
+  C.max_steps = max_steps;
+  BHIP(b, launch_batch_resid(C, (int)b->inst.size(), b->st));
+  return TVLBM_OK;
+}
+
+// One chunk: K steps (the last one also writes the fields), the residual
+// and the compaction of the work list.  At chunk boundaries every instance's
+// post-collision state is in buf[0] (K is even).
+int enqueue_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
+  for (int s = 0; s < K; ++s) {
+    const int mode = (s == K - 1) ? MODE_CHECK : MODE_STEP;
+    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work);
+    if (rc) return rc;
+  }
+  int rc = b->f64 ? batch_resid<double>(b, K, tol, max_steps) : batch_resid<float>(b, K, tol, max_steps);
+  if (rc) return rc;
+  BHIP(b, launch_batch_compact(b->d_active, b->d_item_start, b->d_all, b->d_work, b->d_dst_off,
+                               b->d_nwork, b->d_remaining, (int)b->inst.size(), b->st));
+  return TVLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvlbm_batch_sizes(const tvlbm_batch_desc* d, int64_t* pop_elems, int64_t* field_elems) {
+  if (!d || d->n_inst < 1 || !d->inst) return TVLBM_EINVAL;
+  if (!(d->n_gh == 3 || d->n_gh == 4 || d->n_gh == 6)) return TVLBM_EUNSUPPORTED;
+  std::vector<int64_t> off, fld;
+  std::vector<int32_t> ld;
+  int64_t pop, field;
+  if (!batch_layout(d, d->n_gh * d->n_gh, off, fld, ld, pop, field)) return TVLBM_EINVAL;
+  if (pop_elems) *pop_elems = pop;
+  if (field_elems) *field_elems = field;
+  return TVLBM_OK;
+}
+
+int tvlbm_batch_destroy(tvlbm_batch* b) {
+  if (!b) return TVLBM_EINVAL;
+  if (b->st) hipStreamSynchronize(b->st);
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  hipFree(b->d_insts); hipFree(b->d_all); hipFree(b->d_work); hipFree(b->d_item_start);
+  hipFree(b->d_dst_off); hipFree(b->d_nwork); hipFree(b->d_ntotal); hipFree(b->d_remaining);
+  hipFree(b->d_active); hipFree(b->d_have_prev); hipFree(b->d_steps); hipFree(b->d_resid);
+  hipFree(b->d_flag); hipFree(b->d_fields); hipFree(b->d_prev);
+  if (b->h_remaining) hipHostFree(b->h_remaining);
+  delete b;
+  return TVLBM_OK;
+}
+
+int tvlbm_batch_init(const tvlbm_batch_desc* d, tvlbm_batch** out) {
+  if (!d || !out || d->n_inst < 1 || !d->inst || !d->arena_a || !d->arena_b || d->arena_a == d->arena_b)
+    return TVLBM_EINVAL;
+  if (!d->stream) return TVLBM_EINVAL;  // graph capture needs a non-null stream
+  if (d->dtype != TVLBM_F32 && d->dtype != TVLBM_F64) return TVLBM_EINVAL;
+  *out = nullptr;
+  tvlbm_batch* b = new (std::nothrow) tvlbm_batch();
+  if (!b) return TVLBM_ENOMEM;
+  b->d = *d;
+  b->inst.assign(d->inst, d->inst + d->n_inst);
+  b->d.inst = nullptr;
+  for (const auto& I : b->inst)
+    if (!(I.tau > 0.5)) { delete b; return TVLBM_EINVAL; }
+  if (!build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &b->hl)) { delete b; return TVLBM_EUNSUPPORTED; }
+  b->f64 = d->dtype == TVLBM_F64;
+  b->comp = b->f64 ? false : (d->compensated != 0);
+  b->st = (hipStream_t)d->stream;
+  b->buf[0] = d->arena_a;
+  b->buf[1] = d->arena_b;
+  if (!batch_layout(d, b->hl.q, b->off, b->fld, b->ld, b->pop_elems, b->field_elems)) {
+    delete b;
+    return TVLBM_EINVAL;
+  }
+  fill_lat(b->hl, b->latf);
+  fill_lat(b->hl, b->latd);
+  const int n = d->n_inst;
+  const size_t isz = b->f64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+  std::vector<char> hinst(isz * n);
+  for (int k = 0; k < n; ++k) {
+    const tvlbm_inst& I = b->inst[k];
+    if (b->f64)
+      fill_inst(b->hl, I.tau, 1, 1, I.wall_lo_ux, I.wall_lo_T, I.wall_hi_ux, I.wall_hi_T, I.nx, I.ny,
+                b->ld[k], b->off[k], b->fld[k], *(Inst<double>*)(hinst.data() + isz * k));
+    else
+      fill_inst(b->hl, I.tau, 1, 1, I.wall_lo_ux, I.wall_lo_T, I.wall_hi_ux, I.wall_hi_T, I.nx, I.ny,
+                b->ld[k], b->off[k], b->fld[k], *(Inst<float>*)(hinst.data() + isz * k));
+    ((Inst<float>*)(hinst.data() + isz * k))->id = k;
+  }
+  const size_t esz = b->f64 ? 8 : 4;
+  bool ok = hipMalloc(&b->d_insts, isz * n) == hipSuccess &&
+            hipMalloc(&b->d_item_start, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            hipMalloc(&b->d_dst_off, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc(&b->d_nwork, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_ntotal, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_remaining, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_active, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc(&b->d_have_prev, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc(&b->d_steps, sizeof(int64_t) * n) == hipSuccess &&
+            hipMalloc(&b->d_resid, sizeof(double) * n) == hipSuccess &&
+            hipMalloc(&b->d_flag, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_fields, esz * b->field_elems) == hipSuccess &&
+            hipMalloc(&b->d_prev, esz * b->field_elems) == hipSuccess &&
+            hipHostMalloc((void**)&b->h_remaining, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+  if (!ok) { tvlbm_batch_destroy(b); return TVLBM_ENOMEM; }
+  if (hipMemcpy(b->d_insts, hinst.data(), isz * n, hipMemcpyHostToDevice) != hipSuccess) {
+    tvlbm_batch_destroy(b);
+    return TVLBM_EHIP;
+  }
+  const int32_t zero = 0;
+  if (hipMemcpy(b->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) {
+    tvlbm_batch_destroy(b);
+    return TVLBM_EHIP;
+  }
+  b->shapes = {{16, 16, 8}, {32, 32, 8}, {1 << 30, 64, 8}};
+  if (build_items(b) != TVLBM_OK) { tvlbm_batch_destroy(b); return TVLBM_EHIP; }
+  *out = b;
+  return TVLBM_OK;
+}
+
+int tvlbm_batch_set_shape(tvlbm_batch* b, int32_t max_nx, int32_t width, int32_t rows) {
+  if (!b || !(width == 16 || width == 32 || width == 64) || rows < 1 || rows > 255 || max_nx < 1)
+    return bfail(b, TVLBM_EINVAL, "shape");
+  bool found = false;
+  for (auto& s : b->shapes)
+    if (s.max_nx == max_nx) { s.width = width; s.rows = rows; found = true; }
+  if (!found) b->shapes.push_back({max_nx, width, rows});
+  std::sort(b->shapes.begin(), b->shapes.end(),
+            [](const tvlbm_batch::Shape& x, const tvlbm_batch::Shape& y) { return x.max_nx < y.max_nx; });
+  BHIP(b, hipStreamSynchronize(b->st));
+  return build_items(b);
+}
+
+int tvlbm_batch_set_fields(tvlbm_batch* b, const void* fields) {
+  if (!b || !fields) return bfail(b, TVLBM_EINVAL, "null");
+  for (size_t k = 0; k < b->inst.size(); ++k) {
+    const tvlbm_inst& I = b->inst[k];
+    const int64_t np = (int64_t)I.nx * I.ny;
+    if (b->f64) {
+      InitArgs<double> A;
+      std::memset(&A, 0, sizeof A);
+      A.lat = b->latd;
+      fill_inst(b->hl, I.tau, 1, 1, I.wall_lo_ux, I.wall_lo_T, I.wall_hi_ux, I.wall_hi_T, I.nx, I.ny,
+                b->ld[k], b->off[k], b->fld[k], A.inst);
+      const double* f = (const double*)fields + b->fld[k];
+      A.rho = f; A.ux = f + np; A.uy = f + 2 * np; A.T = f + 3 * np;
+      A.f0 = (double*)b->buf[1];
+      A.g0 = (double*)b->buf[0];
+      BHIP(b, launch_init(b->hl.n, false, A, b->st));
+    } else {
+      InitArgs<float> A;
+      std::memset(&A, 0, sizeof A);
+      A.lat = b->latf;
+      fill_inst(b->hl, I.tau, 1, 1, I.wall_lo_ux, I.wall_lo_T, I.wall_hi_ux, I.wall_hi_T, I.nx, I.ny,
+                b->ld[k], b->off[k], b->fld[k], A.inst);
+      const float* f = (const float*)fields + b->fld[k];
+      A.rho = f; A.ux = f + np; A.uy = f + 2 * np; A.T = f + 3 * np;
+      A.f0 = (float*)b->buf[1];
+      A.g0 = (float*)b->buf[0];
+      BHIP(b, launch_init(b->hl.n, b->comp, A, b->st));
+    }
+  }
+  b->initialised = true;
+  b->stepped = false;
+  return TVLBM_OK;
+}
+
+int tvlbm_batch_run(tvlbm_batch* b, int64_t max_steps, double tol, int32_t K, int64_t* steps_out,
+                    double* r_out) {
+  if (!b || K < 2 || (K & 1) || max_steps < 1 || !steps_out) return bfail(b, TVLBM_EINVAL, "run args");
+  if (!b->initialised) return bfail(b, TVLBM_EINVAL, "fields not set");
+  const int n = (int)b->inst.size();
+  std::vector<int32_t> ones(n, 1), zeros(n, 0);
+  std::vector<int64_t> zeros64(n, 0);
+  BHIP(b, hipMemcpyAsync(b->d_flag, zeros.data(), sizeof(int32_t), hipMemcpyHostToDevice, b->st));
+  BHIP(b, hipMemcpyAsync(b->d_active, ones.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->st));
+  // snapshot of the starting fields, so the first chunk already yields a
+  // residual (as the single-instance solve does)
+  {
+    const int aux = AUX_FIELDS | (b->stepped ? 0 : AUX_IDENTITY);
+    int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all);
+    if (rc) return rc;
+    const size_t esz = b->f64 ? 8 : 4;
+    BHIP(b, hipMemcpyAsync(b->d_prev, b->d_fields, esz * b->field_elems, hipMemcpyDeviceToDevice, b->st));
+  }
+  BHIP(b, hipMemcpyAsync(b->d_have_prev, ones.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->st));
+  BHIP(b, hipMemcpyAsync(b->d_steps, zeros64.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, b->st));
+  BHIP(b, launch_batch_compact(b->d_active, b->d_item_start, b->d_all, b->d_work, b->d_dst_off,
+                               b->d_nwork, b->d_remaining, n, b->st));
+  if (!b->gexec || b->g_K != K || b->g_tol != tol || b->g_max != max_steps) {
+    if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    BHIP(b, hipStreamSynchronize(b->st));
+    BHIP(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_chunk(b, K, tol, max_steps);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->st, &g);
+    if (rc) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return bfail(b, TVLBM_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { b->gexec = nullptr; return bfail(b, TVLBM_EHIP, "graph instantiate"); }
+    b->g_K = K; b->g_tol = tol; b->g_max = max_steps;
+  }
+  const int64_t max_chunks = (max_steps + K - 1) / K + 1;
+  for (int64_t c = 0; c < max_chunks; ++c) {
+    BHIP(b, hipGraphLaunch(b->gexec, b->st));
+    BHIP(b, hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int32_t), hipMemcpyDeviceToHost, b->st));
+    BHIP(b, hipStreamSynchronize(b->st));
+    b->stepped = true;
+    if (*b->h_remaining == 0) break;
+  }
+  std::vector<double> r(n);
+  int32_t flag = 0;
+  BHIP(b, hipMemcpyAsync(steps_out, b->d_steps, sizeof(int64_t) * n, hipMemcpyDeviceToHost, b->st));
+  BHIP(b, hipMemcpyAsync(r.data(), b->d_resid, sizeof(double) * n, hipMemcpyDeviceToHost, b->st));
+  BHIP(b, hipMemcpyAsync(&flag, b->d_flag, sizeof flag, hipMemcpyDeviceToHost, b->st));
+  BHIP(b, hipStreamSynchronize(b->st));
+  if (r_out) std::memcpy(r_out, r.data(), sizeof(double) * n);
+  if (flag) return bfail(b, TVLBM_ENONFINITE, "non-finite residual");
+  for (int k = 0; k < n; ++k)
+    if (!(r[k] < tol)) return bfail(b, TVLBM_ENOTCONVERGED, "step limit reached");
+  return TVLBM_OK;
+}
+
+int tvlbm_batch_fields(tvlbm_batch* b, void* out) {
+  if (!b || !out) return bfail(b, TVLBM_EINVAL, "null");
+  if (!b->initialised) return bfail(b, TVLBM_EINVAL, "fields not set");
+  const int aux = AUX_FIELDS | (b->stepped ? 0 : AUX_IDENTITY);
+  int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all);
+  if (rc) return rc;
+  const size_t esz = b->f64 ? 8 : 4;
+  BHIP(b, hipMemcpyAsync(out, b->d_fields, esz * b->field_elems, hipMemcpyDeviceToDevice, b->st));
+  int32_t flag = 0;
+  BHIP(b, hipMemcpyAsync(&flag, b->d_flag, sizeof flag, hipMemcpyDeviceToHost, b->st));
+  BHIP(b, hipStreamSynchronize(b->st));
+  if (flag) return bfail(b, TVLBM_ENONFINITE, "non-finite moment");
   return TVLBM_OK;
 }
 

@@ -62,7 +62,27 @@ struct Work {      // one wavefront's share of a batched step
   int32_t inst;    // instance index
   int32_t x0;      // first column of the strip
   int32_t seg0;    // first row segment
+  int32_t shape;   // strip width (16, 32, 64) | rows per lane segment << 8
+};
+
+// Non-uniform rows (the rectangular meshes of Sec. III, uniform in x):
+// for y-node b and target row k, the pulled value is
+//   sum_t w[t] X_a(row src[t]) + glo * ghost_lo + ghi * ghost_hi,
+// where w = (overlap of the shifted source row with row k) / dy_k and the
+// ghost weights are the overlaps of the wall-emission intervals.
+template <typename R>
+struct RowTap {
+  int32_t src[3];
   int32_t pad;
+  R w[3];
+  R glo, ghi;
+};
+// Rows whose shifted interval crosses a wall, per y-node b, with the length
+// that crosses (bottom wall for x_b < 0, top wall for x_b > 0).
+template <typename R>
+struct IncRows {
+  int32_t j[4];
+  R len[4];
 };
 
 template <typename R>
@@ -71,7 +91,7 @@ struct MarchArgs {
   Inst<R> inst;           // single-instance launches
   const Inst<R>* insts;   // batched launches (device)
   const Work* work;       // batched launches (device)
-  int32_t n_work;
+  const int32_t* n_work;  // batched launches: live length of the work list
   int32_t width;          // columns per wavefront strip: 16, 32 or 64
   int32_t rows;           // rows per lane segment
   int32_t aux;            // AuxBits for MODE_AUX
@@ -82,6 +102,10 @@ struct MarchArgs {
   R* fields;              // CHECK / AUX_FIELDS: [4][ny][nx] (may be null)
   double* partials;       // CHECK / AUX_FIELDS: [n_blocks][4] FP64 totals
   int32_t* flag;          // set to 1 on rho <= 0, T <= 0 or non-finite
+  const RowTap<R>* taps;  // non-uniform rows: [n][ny]
+  const IncRows<R>* inc;  // non-uniform rows with walls: [n]
+  const double* dy;       // non-uniform rows: [ny] heights
+  const int32_t* rowflag; // bit 0: row pulls the bottom ghost, bit 1: the top
 };
 
 // Fused multiply-add in the working precision (the double builtin would
@@ -89,19 +113,24 @@ struct MarchArgs {
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// ------------------------------------------------------ exact transforms --
-// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest).
+// ------------------------------------------------------ compensation -----
+// Kahan's compensated summation: (s, c) accumulates x with the rounding
+// error of every addition carried in c (the value is s - c).
 template <typename R>
-__device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
-  s = a + b;
-  R z = s - a;
-  e = (a - (s - z)) + (b - z);
+__device__ __forceinline__ void kahan_add(R& s, R& c, R x) {
+  const R y = x - c;
+  const R t = s + y;
+  c = (t - s) - y;
+  s = t;
 }
-// TwoProduct with a fused multiply-add: p + e == a * b exactly.
+// Compensated dot-product term: the product a*b is split exactly into
+// p + e (TwoProduct with a fused multiply-add); p is added with Kahan's
+// scheme and e into a separate low-order accumulator.
 template <typename R>
-__device__ __forceinline__ void two_prod(R a, R b, R& p, R& e) {
-  p = a * b;
-  e = fmaR(a, b, -p);
+__device__ __forceinline__ void kahan_dot(R& s, R& c, R& lo, R a, R b) {
+  const R p = a * b;
+  lo += fmaR(a, b, -p);
+  kahan_add(s, c, p);
 }
 
 // ---------------------------------------------------------------- moments --
@@ -111,9 +140,10 @@ __device__ __forceinline__ void two_prod(R a, R b, R& p, R& e) {
 // from row sums R_a = sum_b d_ab and column sums C_b = sum_a d_ab:
 //   drho = sum_a R_a, jx = sum_a x_a R_a, jy = sum_b x_b C_b,
 //   ed = sum_a x_a^2 R_a + sum_b x_b^2 C_b.
-// COMP: the row/column sums use TwoSum and the dot products use the
-// compensated dot product of Ogita, Rump & Oishi (Dot2), carrying the
-// rounding error of every addition and product in a second accumulator.
+// COMP: every sum is compensated -- Kahan summation for the row and column
+// sums and for drho, and compensated dot products (exact product split plus
+// Kahan summation) for j and ed, with the low-order parts of the row and
+// column sums carried into the dot products.
 template <typename R, int N, bool COMP>
 __device__ __forceinline__ void cell_moments(const Lat<R>& L, const R (&d)[N * N], R& drho,
                                              R& jx, R& jy, R& ed) {
@@ -144,58 +174,60 @@ __device__ __forceinline__ void cell_moments(const Lat<R>& L, const R (&d)[N * N
     }
     drho = r; jx = x; jy = y; ed = e;
   } else {
-    R ra[N], ea[N], cb[N], eb[N];
+    // row sums (hi, -lo) and column sums
+    R rh[N], rc[N], ch[N], cc[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      R s = d[a * N], e = R(0);
+      R s = d[a * N], c = R(0);
 #pragma unroll
-      for (int b = 1; b < N; ++b) {
-        R t;
-        two_sum(s, d[a * N + b], s, t);
-        e += t;
-      }
-      ra[a] = s; ea[a] = e;
+      for (int b = 1; b < N; ++b) kahan_add(s, c, d[a * N + b]);
+      rh[a] = s; rc[a] = c;
     }
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      R s = d[b], e = R(0);
+      R s = d[b], c = R(0);
+#pragma unroll
+      for (int a = 1; a < N; ++a) kahan_add(s, c, d[a * N + b]);
+      ch[b] = s; cc[b] = c;
+    }
+    {  // drho = sum_a (rh_a - rc_a)
+      R s = rh[0], c = R(0), lo = -rc[0];
 #pragma unroll
       for (int a = 1; a < N; ++a) {
-        R t;
-        two_sum(s, d[a * N + b], s, t);
-        e += t;
+        kahan_add(s, c, rh[a]);
+        lo -= rc[a];
       }
-      cb[b] = s; eb[b] = e;
+      drho = s + (lo - c);
     }
-    // drho
-    R s = ra[0], e = ea[0];
-#pragma unroll
-    for (int a = 1; a < N; ++a) {
-      R t;
-      two_sum(s, ra[a], s, t);
-      e += t + ea[a];
-    }
-    drho = s + e;
-    // Dot2 helpers over (coefficient, hi, lo) triples
-    auto dot2 = [&](const R* c, const R* hi, const R* lo, R& S, R& E) {
+    {  // jx = sum_a x_a (rh_a - rc_a)
+      R s = R(0), c = R(0), lo = R(0);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        R p, ep, t;
-        two_prod(c[a], hi[a], p, ep);
-        two_sum(S, p, S, t);
-        E += t + fmaR(c[a], lo[a], ep);
+        kahan_dot(s, c, lo, L.x[a], rh[a]);
+        lo = fmaR(-L.x[a], rc[a], lo);
       }
-    };
-    R Sx = R(0), Ex = R(0);
-    dot2(L.x, ra, ea, Sx, Ex);
-    jx = Sx + Ex;
-    R Sy = R(0), Ey = R(0);
-    dot2(L.x, cb, eb, Sy, Ey);
-    jy = Sy + Ey;
-    R Se = R(0), Ee = R(0);
-    dot2(L.x2, ra, ea, Se, Ee);
-    dot2(L.x2, cb, eb, Se, Ee);
-    ed = Se + Ee;
+      jx = s + (lo - c);
+    }
+    {  // jy = sum_b x_b (ch_b - cc_b)
+      R s = R(0), c = R(0), lo = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        kahan_dot(s, c, lo, L.x[b], ch[b]);
+        lo = fmaR(-L.x[b], cc[b], lo);
+      }
+      jy = s + (lo - c);
+    }
+    {  // ed = sum_a x_a^2 (rh_a - rc_a) + sum_b x_b^2 (ch_b - cc_b)
+      R s = R(0), c = R(0), lo = R(0);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        kahan_dot(s, c, lo, L.x2[a], rh[a]);
+        lo = fmaR(-L.x2[a], rc[a], lo);
+        kahan_dot(s, c, lo, L.x2[a], ch[a]);
+        lo = fmaR(-L.x2[a], cc[a], lo);
+      }
+      ed = s + (lo - c);
+    }
   }
 }
 
@@ -223,21 +255,26 @@ __device__ __forceinline__ Fields<R> fields_from(R drho, R jx, R jy, R ed) {
 
 // ------------------------------------------------------------ equilibrium --
 // Hermite equilibrium (Sec. II; scalar form of Appendix A) in deviation form:
-//   feq_l - w_l = w_l [ drho + rho (P_l - 1) ],
-//   P_l - 1 = u_l + 1/2 (u_l^2 - u^2 + th (c2 - D))
-//           + (u_l / 6)(u_l^2 - 3 u^2 + 3 th (c2 - D - 2))             [ORD>=3]
-//           + (u_l^4 - 6 u_l^2 u^2 + 3 u^4)/24
-//           + (th/4)((c2 - D - 2)(u_l^2 - u^2) - 2 u_l^2)
-//           + (th^2/8)(c2^2 - 2(D+2) c2 + D(D+2))                      [ORD>=4]
-// with u_l = u.xi_l, c2 = |xi_l|^2, th = T - 1.  The per-cell scalars are
-// hoisted into EqCell; per population the cost is a handful of FMAs.
+//   feq_l - w_l = w_l [ drho + rho P_l ],
+//   P_l = u_l + 1/2 (u_l^2 - u^2 + th cD)
+//       + (u_l / 6)(u_l^2 - 3 u^2 + 3 th (cD - 2))                       [ORD>=3]
+//       + (u_l^4 - 6 u_l^2 u^2 + 3 u^4)/24
+//       + (th/4)((cD - 2)(u_l^2 - u^2) - 2 u_l^2) + th^2 c4              [ORD>=4]
+// with u_l = u.xi_l, th = T - 1, cD = |xi_l|^2 - D and
+// c4 = (|xi_l|^4 - 2(D+2)|xi_l|^2 + D(D+2))/8.  Collecting powers of s = u_l,
+//   P_l = k0 + s (k1 + s (k2 + s (1/6 + s/24)))
+//   k0 = -u^2/2 + (th/2) cD                  [+ u^4/8 + th u^2/2 + th^2 c4 - th u^2 cD/4]
+//   k1 = 1 - u^2/2 - th + (th/2) cD
+//   k2 = 1/2                                 [- u^2/4 - th + th cD/4]
+// (bracketed terms for order 4; order 3 drops the s^4 term; order 2 keeps
+// k0 = -u^2/2 + (th/2) cD, k1 = 1, k2 = 1/2 and no s^3 term).
 template <typename R>
 struct EqCell {
   R ua[NMAX], vb[NMAX];  // x_a ux, x_b uy
-  R u2, th, th3, k3, u2x6, u2sq8, th4, thsq;
+  R g0, be, al, mu, a2, thq, thsq;
 };
 
-template <typename R, int N>
+template <typename R, int N, int ORD>
 __device__ __forceinline__ EqCell<R> eq_cell(const Lat<R>& L, const Fields<R>& F) {
   EqCell<R> E;
 #pragma unroll
@@ -245,38 +282,49 @@ __device__ __forceinline__ EqCell<R> eq_cell(const Lat<R>& L, const Fields<R>& F
     E.ua[a] = L.x[a] * F.ux;
     E.vb[a] = L.x[a] * F.uy;
   }
-  E.u2 = F.ux * F.ux + F.uy * F.uy;
-  E.th = F.th;
-  E.th3 = R(3) * F.th;
-  E.k3 = R(-2) * E.u2 - R(6) * F.th;
-  E.u2x6 = R(6) * E.u2;
-  E.u2sq8 = E.u2 * E.u2 * R(0.125);
-  E.th4 = F.th * R(0.25);
-  E.thsq = F.th * F.th;
+  const R u2 = F.ux * F.ux + F.uy * F.uy;
+  const R th = F.th;
+  E.be = R(0.5) * th;
+  E.thq = R(0.25) * th;
+  E.thsq = th * th;
+  if constexpr (ORD >= 3) {
+    E.al = R(1) - R(0.5) * u2 - th;
+  } else {
+    E.al = R(1);
+  }
+  if constexpr (ORD >= 4) {
+    E.g0 = -R(0.5) * u2 + u2 * (R(0.125) * u2 + E.be);
+    E.mu = E.be - E.thq * u2;
+    E.a2 = R(0.5) - R(0.25) * u2 - th;
+  } else {
+    E.g0 = -R(0.5) * u2;
+    E.mu = E.be;
+    E.a2 = R(0.5);
+  }
   return E;
 }
 
-// returns P_l - 1
+// returns P_l (the equilibrium polynomial minus its leading 1)
 template <typename R, int N, int ORD>
 __device__ __forceinline__ R eq_poly(const Lat<R>& L, const EqCell<R>& E, int a, int b) {
   const int l = a * N + b;
-  R ul = E.ua[a] + E.vb[b];
-  R ul2 = ul * ul;
-  R d2 = ul2 - E.u2;
-  R A = fmaR(E.th, L.cD[l], d2);
-  R P = fmaR(R(0.5), A, ul);
-  if constexpr (ORD >= 3) {
-    R B = fmaR(E.th3, L.cD[l], d2 + E.k3);
-    P = fmaR(ul * R(1.0 / 6.0), B, P);
-  }
+  const R s = E.ua[a] + E.vb[b];
+  const R cD = L.cD[l];
+  R k0 = fmaR(cD, E.mu, E.g0);
+  if constexpr (ORD >= 4) k0 = fmaR(E.thsq, L.c4[l], k0);
+  const R k1 = (ORD >= 3) ? fmaR(cD, E.be, E.al) : E.al;
+  R h;
   if constexpr (ORD >= 4) {
-    R q4 = ul2 * (ul2 - E.u2x6) * R(1.0 / 24.0) + E.u2sq8;
-    R m = (L.cD[l] - R(2)) * d2 - R(2) * ul2;
-    q4 = fmaR(E.th4, m, q4);
-    q4 = fmaR(E.thsq, L.c4[l], q4);
-    P += q4;
+    const R k2 = fmaR(cD, E.thq, E.a2);
+    h = fmaR(s, R(1.0 / 24.0), R(1.0 / 6.0));
+    h = fmaR(s, h, k2);
+  } else if constexpr (ORD == 3) {
+    h = fmaR(s, R(1.0 / 6.0), E.a2);
+  } else {
+    h = E.a2;
   }
-  return P;
+  h = fmaR(s, h, k1);
+  return fmaR(s, h, k0);
 }
 
 // BGK update in deviation form (eq.(lb) integrated over one step, tau in

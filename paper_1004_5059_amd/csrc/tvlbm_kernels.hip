@@ -32,17 +32,31 @@ __host__ __device__ constexpr int node_sign(int a) {
   return (2 * a + 1 < N) ? -1 : ((2 * a + 1 > N) ? 1 : 0);
 }
 
-// Element load at the wave-uniform instance base plus a 32-bit element
-// offset (population plane + row + column; the host guarantees the whole
-// instance block is below 4 GiB), which maps to the SGPR-base + VGPR-offset
-// addressing mode of global loads and stores.
-template <typename R>
-__device__ __forceinline__ R ldo(const R* __restrict__ base, uint32_t e) {
-  return *(const R*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(R)));
+// Buffer addressing: one resource per instance block (base and size in
+// SGPRs); the lane offset (row, column) is a VGPR and the population plane
+// offset l * plane is a wave-uniform SGPR offset, so no per-load address
+// arithmetic is spent on the vector ALUs.  Accesses beyond the block return
+// zero instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 template <typename R>
-__device__ __forceinline__ void sto(R* __restrict__ base, uint32_t e, R v) {
-  *(R*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(R))) = v;
+__device__ __forceinline__ R bld(rsrc_t r, uint32_t v, uint32_t s);
+template <>
+__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t v, uint32_t s) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v * 4u, s * 4u, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t v, uint32_t s) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8u, s * 8u, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, v * 4u, s * 4u, 0);
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, double x) {
+  using v2i = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, x), r, v * 8u, s * 8u, 0);
 }
 
 // Lane offsets of one row: centre, left and right neighbour (periodic in x).
@@ -56,12 +70,11 @@ __device__ __forceinline__ RowOff row_off(uint32_t rowbase, int ic, int im, int 
 // x part of the overlap remap for node a: value landing in the centre
 // column from the centre (weight 1-p) and the upstream column (weight p).
 template <typename R, int N>
-__device__ __forceinline__ R xpull(const Lat<R>& L, const R* __restrict__ s, uint32_t lo, int a,
-                                   const RowOff& o) {
+__device__ __forceinline__ R xpull(const Lat<R>& L, rsrc_t s, uint32_t lo, int a, const RowOff& o) {
   const int sg = node_sign<N>(a);
-  R vc = ldo(s, lo + o.c);
-  if (sg > 0) return fmaR(L.qm[a], vc, L.p[a] * ldo(s, lo + o.m));
-  if (sg < 0) return fmaR(L.qm[a], vc, L.p[a] * ldo(s, lo + o.p));
+  R vc = bld<R>(s, o.c, lo);
+  if (sg > 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.m, lo));
+  if (sg < 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.p, lo));
   return vc;
 }
 
@@ -70,7 +83,7 @@ __device__ __forceinline__ R xpull(const Lat<R>& L, const R* __restrict__ s, uin
 // wall, landing in column c:  m(c) = sum_{b: sign(x_b)=dir} p_b sum_a X_a(d_ab)(c).
 // The rest-state part sum p_b w_b is folded into the host constants kap_*.
 template <typename R, int N>
-__device__ __forceinline__ R wall_mass(const Lat<R>& L, const R* __restrict__ s, int64_t plane,
+__device__ __forceinline__ R wall_mass(const Lat<R>& L, rsrc_t s, int64_t plane,
                                        uint32_t rowbase, int c, int nx, int dir) {
   const RowOff o = row_off(rowbase, c, wrapc(c - 1, nx), wrapc(c + 1, nx));
   R m = R(0);
@@ -95,12 +108,88 @@ __device__ __forceinline__ R ghost_pull(const Lat<R>& L, int a, R kap, R phi, R 
   return fmaR(phi, mx, kap);
 }
 
+// Moments, equilibrium, collision and outputs of one cell whose pulled
+// (post-stream, pre-collision) deviations are d[].  dyj: row height (for the
+// area-weighted totals).
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& P, rsrc_t dst,
+                                          const R (&d)[N * N], int j, int i, bool active,
+                                          double dyj, double (&tot)[4], int& bad) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const int nx = P.nx, ny = P.ny;
+  R drho, jx, jy, ed;
+  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<R> F = fields_from(drho, jx, jy, ed);
+
+  if constexpr (MODE != MODE_STEP) {
+    const bool want_fields = (MODE == MODE_CHECK) || (A.aux & AUX_FIELDS);
+    if (want_fields && active) {
+      const R T = R(1) + F.th;
+      if (!(F.rho > R(0)) || !(T > R(0)) || !__builtin_isfinite(F.ux + F.uy + F.rho + T)) bad = 1;
+      if (A.fields) {
+        R* fo = A.fields + P.fld + (int64_t)j * nx + i;
+        const int64_t fp = (int64_t)nx * ny;
+        fo[0] = F.rho;
+        fo[fp] = F.ux;
+        fo[2 * fp] = F.uy;
+        fo[3 * fp] = T;
+      }
+      double m = 0.0, px = 0.0, py = 0.0, e = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const double fa = L.wd[l] + (double)d[l];
+          m += fa;
+          px += L.xd[a] * fa;
+          py += L.xd[b] * fa;
+          e += 0.5 * (L.xd[a] * L.xd[a] + L.xd[b] * L.xd[b]) * fa;
+        }
+      }
+      tot[0] += dyj * m; tot[1] += dyj * px; tot[2] += dyj * py; tot[3] += dyj * e;
+    }
+  }
+
+  if constexpr (MODE == MODE_AUX) {
+    if (A.aux & AUX_POPS) {
+      if (active) {
+        const int64_t op = (int64_t)nx * ny;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) A.dst[l * op + (int64_t)j * nx + i] = d[l] + L.w[l];
+      }
+      return;
+    }
+    if (!(A.aux & AUX_POST)) return;
+  }
+
+  const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      const R Pl = eq_poly<R, N, ORD>(L, E, a, b);
+      const R g = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, Pl);
+      if (active) {
+        if constexpr (MODE == MODE_AUX) {
+          const int64_t op = (int64_t)nx * ny;
+          A.dst[l * op + (int64_t)j * nx + i] = g + L.w[l];
+        } else {
+          bst(dst, (uint32_t)j * (uint32_t)P.ld + (uint32_t)i, (uint32_t)(l * P.plane), g);
+        }
+      }
+    }
+  }
+}
+
 // Everything one lane does for one row j: pull, moments, equilibrium,
 // collision, store (or the auxiliary outputs).  GHOST_HI: row j is the last
 // row of a walled channel and the downward populations pull the top ghost.
 template <typename R, int N, int ORD, bool COMP, int MODE, bool GHOST_HI>
 __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& P,
-                                          const R* __restrict__ s, R (&hp)[N * N], int j,
+                                          rsrc_t s, rsrc_t dst, R (&hp)[N * N], int j,
                                           int i, int ic, int im, int ip, bool active,
                                           bool ident, double (&tot)[4], int& bad) {
   constexpr int Q = N * N;
@@ -111,7 +200,7 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
   R d[Q];
   if (ident) {
 #pragma unroll
-    for (int l = 0; l < Q; ++l) d[l] = ldo(s, (uint32_t)(l * plane) + rj + (uint32_t)ic);
+    for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, rj + (uint32_t)ic, (uint32_t)(l * plane));
   } else {
     const RowOff oj = row_off(rj, ic, im, ip);
     const uint32_t rn = (j + 1 == ny) ? 0u : rj + (uint32_t)P.ld;
@@ -148,70 +237,7 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
     }
   }
 
-  R drho, jx, jy, ed;
-  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
-  const Fields<R> F = fields_from(drho, jx, jy, ed);
-
-  if constexpr (MODE != MODE_STEP) {
-    const bool want_fields = (MODE == MODE_CHECK) || (A.aux & AUX_FIELDS);
-    if (want_fields && active) {
-      const R T = R(1) + F.th;
-      if (!(F.rho > R(0)) || !(T > R(0)) || !__builtin_isfinite(F.ux + F.uy + F.rho + T)) bad = 1;
-      if (A.fields) {
-        R* fo = A.fields + P.fld + (int64_t)j * nx + i;
-        const int64_t fp = (int64_t)nx * ny;
-        fo[0] = F.rho;
-        fo[fp] = F.ux;
-        fo[2 * fp] = F.uy;
-        fo[3 * fp] = T;
-      }
-      double m = 0.0, px = 0.0, py = 0.0, e = 0.0;
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          const int l = a * N + b;
-          const double fa = L.wd[l] + (double)d[l];
-          m += fa;
-          px += L.xd[a] * fa;
-          py += L.xd[b] * fa;
-          e += 0.5 * (L.xd[a] * L.xd[a] + L.xd[b] * L.xd[b]) * fa;
-        }
-      }
-      tot[0] += m; tot[1] += px; tot[2] += py; tot[3] += e;
-    }
-  }
-
-  if constexpr (MODE == MODE_AUX) {
-    if (A.aux & AUX_POPS) {
-      if (active) {
-        const int64_t op = (int64_t)nx * ny;
-#pragma unroll
-        for (int l = 0; l < Q; ++l) A.dst[l * op + (int64_t)j * nx + i] = d[l] + L.w[l];
-      }
-      return;
-    }
-    if (!(A.aux & AUX_POST)) return;
-  }
-
-  const EqCell<R> E = eq_cell<R, N>(L, F);
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      const R Pl = eq_poly<R, N, ORD>(L, E, a, b);
-      const R g = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, Pl);
-      if (active) {
-        if constexpr (MODE == MODE_AUX) {
-          const int64_t op = (int64_t)nx * ny;
-          A.dst[l * op + (int64_t)j * nx + i] = g + L.w[l];
-        } else {
-          sto(A.dst + P.off, (uint32_t)(l * plane) + rj + (uint32_t)i, g);
-        }
-      }
-    }
-  }
+  cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, j, i, active, 1.0, tot, bad);
 }
 
 template <typename R, int N, int ORD, bool COMP, int MODE>
@@ -222,7 +248,9 @@ __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>&
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
   const int64_t plane = P.plane;
-  const R* __restrict__ s = A.src + P.off;
+  const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(R));
+  const rsrc_t s = make_rsrc(A.src + P.off, bytes);
+  const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
   const int ic = active ? i : 0;  // inactive lanes read a valid column, store nothing
   const int im = ic == 0 ? nx - 1 : ic - 1;
   const int ip = ic == nx - 1 ? 0 : ic + 1;
@@ -259,12 +287,12 @@ __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>&
 
   const int jmain = (P.walls && j1 == ny) ? j1 - 1 : j1;
   for (int j = j0; j < jmain; ++j)
-    march_row<R, N, ORD, COMP, MODE, false>(A, P, s, hp, j, i, ic, im, ip, active, ident, tot, bad);
+    march_row<R, N, ORD, COMP, MODE, false>(A, P, s, dst, hp, j, i, ic, im, ip, active, ident, tot, bad);
   if (jmain < j1) {
     if (ident)
-      march_row<R, N, ORD, COMP, MODE, false>(A, P, s, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
+      march_row<R, N, ORD, COMP, MODE, false>(A, P, s, dst, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
     else
-      march_row<R, N, ORD, COMP, MODE, true>(A, P, s, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
+      march_row<R, N, ORD, COMP, MODE, true>(A, P, s, dst, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
   }
 }
 
@@ -316,6 +344,214 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
   }
 }
 
+
+// ------------------------------------------------------- non-uniform rows --
+// Wall mass through a wall with non-uniform rows: the rows listed in inc[b]
+// carry the length len across the wall.
+template <typename R, int N>
+__device__ __forceinline__ R wall_mass_rows(const Lat<R>& L, const IncRows<R>* __restrict__ inc,
+                                            rsrc_t s, int64_t plane, uint32_t ld, int c, int nx,
+                                            int dir) {
+  const int cm = wrapc(c - 1, nx), cp = wrapc(c + 1, nx);
+  R m = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    if (node_sign<N>(b) != dir) continue;
+    const IncRows<R>& I = inc[b];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (I.len[t] == R(0)) continue;
+      const RowOff o = row_off((uint32_t)I.j[t] * ld, c, cm, cp);
+      R acc = R(0);
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc += xpull<R, N>(L, s, (uint32_t)((a * N + b) * plane), a, o);
+      m = fmaR(I.len[t], acc, m);
+    }
+  }
+  return m;
+}
+
+// One cell of a grid with tabulated (non-uniform) rows.
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& P, rsrc_t s,
+                                          rsrc_t dst, int k, int i, bool active, double (&tot)[4],
+                                          int& bad) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const int nx = P.nx, ny = P.ny;
+  const int64_t plane = P.plane;
+  const uint32_t ld = (uint32_t)P.ld;
+  const int ic = active ? i : 0;
+  const int im = ic == 0 ? nx - 1 : ic - 1;
+  const int ip = ic == nx - 1 ? 0 : ic + 1;
+  R d[Q];
+  if ((MODE == MODE_AUX) && (A.aux & AUX_IDENTITY)) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, (uint32_t)k * ld + (uint32_t)ic, (uint32_t)(l * plane));
+  } else {
+    const int flag = A.rowflag[k];
+    R lo_c = R(0), lo_m = R(0), lo_p = R(0), hi_c = R(0), hi_m = R(0), hi_p = R(0);
+    if (flag & 1) {
+      lo_c = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ic, nx, -1);
+      lo_m = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, im, nx, -1);
+      lo_p = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ip, nx, -1);
+    }
+    if (flag & 2) {
+      hi_c = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ic, nx, +1);
+      hi_m = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, im, nx, +1);
+      hi_p = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ip, nx, +1);
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const RowTap<R>& T = A.taps[b * ny + k];
+      RowOff o[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) o[t] = row_off((uint32_t)T.src[t] * ld, ic, im, ip);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const int l = a * N + b;
+        const uint32_t pl = (uint32_t)(l * plane);
+        R acc = R(0);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          if (T.w[t] != R(0)) acc = fmaR(T.w[t], xpull<R, N>(L, s, pl, a, o[t]), acc);
+        if ((flag & 1) && T.glo != R(0))
+          acc = fmaR(T.glo, ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], lo_c, lo_m, lo_p), acc);
+        if ((flag & 2) && T.ghi != R(0))
+          acc = fmaR(T.ghi, ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], hi_c, hi_m, hi_p), acc);
+        d[l] = acc;
+      }
+    }
+  }
+  cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, k, i, active, A.dy[k], tot, bad);
+}
+
+// Non-uniform-row step: a workgroup covers 64 columns x 4 rows, one row per
+// wavefront, so every row-table read is wave-uniform.
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__global__ __launch_bounds__(256) void k_rows(const MarchArgs<R> A) {
+  constexpr int Q = N * N;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  int bad = 0;
+  const Inst<R>& P = A.inst;
+  if (t < A.n_tiles) {
+    const int tx = t % A.tiles_x, ty = t / A.tiles_x;
+    const int i = tx * 64 + lane;
+    const int k = ty * 4 + wave;
+    if (k < P.ny) {
+      const uint32_t bytes = (uint32_t)(Q * P.plane * (int64_t)sizeof(R));
+      const rsrc_t s = make_rsrc(A.src + P.off, bytes);
+      const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
+      rows_cell<R, N, ORD, COMP, MODE>(A, P, s, dst, k, i, i < P.nx, tot, bad);
+    }
+  }
+  if constexpr (MODE != MODE_STEP) {
+    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
+  }
+}
+
+
+// ---------------------------------------------------------------- batched --
+// Persistent grid-stride step over a device-resident work list: each
+// wavefront takes work items (instance, strip, segment group) until the
+// list, whose live length is read from device memory, is exhausted.  The
+// per-instance parameters are read from device memory with scalar loads.
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_work = *A.n_work;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  int bad = 0;
+  for (int w = blockIdx.x * 4 + wave; w < n_work; w += gridDim.x * 4) {
+    const Work it = A.work[w];
+    const Inst<R>& P = A.insts[it.inst];
+    const int W = it.shape & 0xff, rows = it.shape >> 8;
+    const int i = it.x0 + (lane & (W - 1));
+    const int seg = it.seg0 + lane / W;
+    const int j0 = seg * rows;
+    const int j1 = min(j0 + rows, P.ny);
+    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE>(A, P, i, i < P.nx, j0, j1, tot, bad);
+  }
+  if constexpr (MODE != MODE_STEP) {
+    if (bad) A.flag[0] = 1;
+  }
+}
+
+// Per-instance residual after a chunk of K steps (one workgroup per
+// instance): r = ||q - q_prev|| / (K ||q||) over the instance's stacked
+// fields; the snapshot is updated, the step count advanced, and the instance
+// retired when r < tol or its step budget is spent.
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_resid(const BatchCtl<R> C) {
+  __shared__ double sh[2][4];
+  const int b = blockIdx.x;
+  if (!C.active[b]) return;
+  const Inst<R>& P = C.insts[b];
+  const int64_t n = (int64_t)4 * P.nx * P.ny;
+  const R* q = C.fields + P.fld;
+  R* qp = C.prev + P.fld;
+  double a = 0.0, s = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) {
+    const double v = (double)q[k], dv = v - (double)qp[k];
+    a += dv * dv;
+    s += v * v;
+    qp[k] = q[k];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    s += __shfl_xor(s, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sh[0][wave] = a; sh[1][wave] = s; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double A2 = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+    const double S2 = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    const int64_t st = C.steps[b] + C.K;
+    C.steps[b] = st;
+    const double r = C.have_prev[b] ? __builtin_sqrt(A2) / ((double)C.K * __builtin_sqrt(S2))
+                                    : __builtin_inf();
+    C.have_prev[b] = 1;
+    C.resid[b] = r;
+    if (!(r == r)) C.flag[0] = 1;
+    if (!(r >= C.tol) || st >= C.max_steps) C.active[b] = 0;
+  }
+}
+
+// Rebuild the work list from the active instances (single workgroup).
+__global__ __launch_bounds__(256) void k_batch_compact(const int32_t* __restrict__ active,
+                                                       const int32_t* __restrict__ item_start,
+                                                       const Work* __restrict__ all,
+                                                       Work* __restrict__ work,
+                                                       int32_t* __restrict__ dst_off,
+                                                       int32_t* __restrict__ n_work,
+                                                       int32_t* __restrict__ remaining,
+                                                       int n_inst) {
+  if (threadIdx.x == 0) {
+    int o = 0, rem = 0;
+    for (int b = 0; b < n_inst; ++b) {
+      dst_off[b] = o;
+      if (active[b]) {
+        o += item_start[b + 1] - item_start[b];
+        ++rem;
+      }
+    }
+    *n_work = o;
+    *remaining = rem;
+  }
+  __syncthreads();
+  for (int b = 0; b < n_inst; ++b) {
+    if (!active[b]) continue;
+    const int s0 = item_start[b], cnt = item_start[b + 1] - s0, o = dst_off[b];
+    for (int t = threadIdx.x; t < cnt; t += 256) work[o + t] = all[s0 + t];
+  }
+}
+
 // ----------------------------------------------------------------- init ---
 // f^0 (deviations) into `f0`, and g^0 = C(f^0) into `g0`, pitch ld.
 template <typename R, int N, int ORD, bool COMP>
@@ -338,7 +574,7 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
     F.ux = A.ux[c];
     F.uy = A.uy[c];
     F.th = A.T[c] - R(1);
-    const EqCell<R> E = eq_cell<R, N>(L, F);
+    const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
 #pragma unroll
     for (int a = 0; a < N; ++a)
 #pragma unroll
@@ -354,7 +590,7 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
-  const EqCell<R> E = eq_cell<R, N>(L, F);
+  const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
 #pragma unroll
   for (int a = 0; a < N; ++a)
 #pragma unroll
@@ -411,6 +647,14 @@ __global__ __launch_bounds__(256) void k_resid(const R* __restrict__ q, const R*
 template <typename R, int N, int ORD, bool COMP>
 static hipError_t march_mode(int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
   dim3 g(nblocks), b(256);
+  if (A.taps) {
+    switch (mode) {
+      case MODE_STEP: hipLaunchKernelGGL((k_rows<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
+      case MODE_CHECK: hipLaunchKernelGGL((k_rows<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
+      default: hipLaunchKernelGGL((k_rows<R, N, ORD, COMP, MODE_AUX>), g, b, 0, st, A); break;
+    }
+    return hipGetLastError();
+  }
   switch (mode) {
     case MODE_STEP: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
     case MODE_CHECK: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
@@ -459,6 +703,55 @@ hipError_t launch_init(int n, bool comp, const InitArgs<float>& A, hipStream_t s
 hipError_t launch_init(int n, bool comp, const InitArgs<double>& A, hipStream_t st) {
   (void)comp;
   return init_lat<double, false>(n, A, st);
+}
+
+template <typename R, int N, int ORD, bool COMP>
+static hipError_t batch_mode(int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (mode) {
+    case MODE_STEP: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
+    case MODE_CHECK: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_AUX>), g, b, 0, st, A); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename R, bool COMP>
+static hipError_t batch_lat(int n, int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  switch (n) {
+    case 3: return batch_mode<R, 3, 2, COMP>(mode, A, nblocks, st);
+    case 4: return batch_mode<R, 4, 3, COMP>(mode, A, nblocks, st);
+    case 6: return batch_mode<R, 6, 4, COMP>(mode, A, nblocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
+                              hipStream_t st) {
+  return comp ? batch_lat<float, true>(n, mode, A, nblocks, st)
+              : batch_lat<float, false>(n, mode, A, nblocks, st);
+}
+hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
+                              hipStream_t st) {
+  (void)comp;
+  return batch_lat<double, false>(n, mode, A, nblocks, st);
+}
+
+hipError_t launch_batch_resid(const BatchCtl<float>& C, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_resid<float>, dim3(n_inst), dim3(256), 0, st, C);
+  return hipGetLastError();
+}
+hipError_t launch_batch_resid(const BatchCtl<double>& C, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_resid<double>, dim3(n_inst), dim3(256), 0, st, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start, const Work* all,
+                                Work* work, int32_t* dst_off, int32_t* n_work, int32_t* remaining,
+                                int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(256), 0, st, active, item_start, all, work,
+                     dst_off, n_work, remaining, n_inst);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t st) {

@@ -19,6 +19,31 @@ struct InitArgs {
   R* g0;           // deviations C(f^0), pitch ld
 };
 
+// Control block of a batched run (device arrays, n_inst entries each).
+template <typename R>
+struct BatchCtl {
+  const Inst<R>* insts;
+  const R* fields;     // packed fields of the last check step
+  R* prev;             // packed snapshot of the previous check
+  int32_t* active;
+  int32_t* have_prev;
+  int64_t* steps;
+  double* resid;
+  int32_t* flag;
+  int32_t K;
+  double tol;
+  int64_t max_steps;
+};
+
+hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
+                              hipStream_t st);
+hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
+                              hipStream_t st);
+hipError_t launch_batch_resid(const BatchCtl<float>& C, int n_inst, hipStream_t st);
+hipError_t launch_batch_resid(const BatchCtl<double>& C, int n_inst, hipStream_t st);
+hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start, const Work* all,
+                                Work* work, int32_t* dst_off, int32_t* n_work, int32_t* remaining,
+                                int n_inst, hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
                         hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,

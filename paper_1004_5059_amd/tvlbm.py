@@ -60,6 +60,34 @@ class tvlbm_desc(ctypes.Structure):
     ]
 
 
+class tvlbm_inst(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("wall_lo_ux", ctypes.c_double),
+        ("wall_lo_T", ctypes.c_double),
+        ("wall_hi_ux", ctypes.c_double),
+        ("wall_hi_T", ctypes.c_double),
+    ]
+
+
+class tvlbm_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_gh", ctypes.c_int32),
+        ("eq_order", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("compensated", ctypes.c_int32),
+        ("cfl", ctypes.c_double),
+        ("cfl_norm", ctypes.c_int32),
+        ("n_inst", ctypes.c_int32),
+        ("inst", ctypes.POINTER(tvlbm_inst)),
+        ("arena_a", ctypes.c_void_p),
+        ("arena_b", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 class TvlbmError(RuntimeError):
     def __init__(self, code: int, detail: str = ""):
         self.code = code
@@ -100,6 +128,13 @@ def lib():
         "tvlbm_set_variant": [_vp, ctypes.c_int32],
         "tvlbm_strerror": [ctypes.c_int],
         "tvlbm_last_error": [_vp],
+        "tvlbm_batch_sizes": [ctypes.POINTER(tvlbm_batch_desc), _i64p, _i64p],
+        "tvlbm_batch_init": [ctypes.POINTER(tvlbm_batch_desc), ctypes.POINTER(_vp)],
+        "tvlbm_batch_destroy": [_vp],
+        "tvlbm_batch_set_fields": [_vp, _vp],
+        "tvlbm_batch_run": [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _i64p, _dp],
+        "tvlbm_batch_fields": [_vp, _vp],
+        "tvlbm_batch_set_shape": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -230,7 +265,7 @@ class Solver:
     def __init__(self, nx: int, ny: int, n_gh: int = 4, dtype: str = "f32", tau: float = 0.8,
                  cfl: float = 0.9, cfl_norm: int = TVLBM_CFL_EUCLID, collide: bool = True,
                  walls: bool = False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0),
-                 compensated: bool = True, ld: int = 0, device=None, stream=None):
+                 compensated: bool = True, ld: int = 0, dy=None, device=None, stream=None):
         import torch
 
         self.torch = torch
@@ -256,7 +291,12 @@ class Solver:
         d.compensated = int(compensated)
         d.wall_lo_ux, d.wall_lo_T = wall_lo
         d.wall_hi_ux, d.wall_hi_T = wall_hi
-        d.dy = None
+        self._dy = None
+        if dy is not None:
+            self._dy = (ctypes.c_double * ny)(*[float(v) for v in dy])
+            d.dy = ctypes.cast(self._dy, ctypes.POINTER(ctypes.c_double))
+        else:
+            d.dy = None
         d.f_a = self.f_a.data_ptr()
         d.f_b = self.f_b.data_ptr()
         d.stream = self.stream.cuda_stream
@@ -275,7 +315,7 @@ class Solver:
             pass
 
     def _dev(self, a, shape):
-        t = self.torch.as_tensor(np.ascontiguousarray(np.broadcast_to(a, shape)), dtype=self.tdtype)
+        t = self.torch.as_tensor(np.array(np.broadcast_to(a, shape)), dtype=self.tdtype)
         return t.to(self.device)
 
     def set_fields(self, rho, ux, uy, T, noise=None):
@@ -324,3 +364,138 @@ class Solver:
 
     def set_variant(self, v: int):
         tvlbm_set_variant(self.ctx, v)
+
+
+# ----------------------------------------------------------------- batched --
+def tvlbm_batch_sizes(desc: tvlbm_batch_desc):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().tvlbm_batch_sizes(ctypes.byref(desc), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tvlbm_batch_init(desc: tvlbm_batch_desc):
+    h = _vp()
+    _check(lib().tvlbm_batch_init(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def tvlbm_batch_destroy(h):
+    _check(lib().tvlbm_batch_destroy(h))
+
+
+def tvlbm_batch_set_fields(h, fields):
+    _check(lib().tvlbm_batch_set_fields(h, _ptr(fields)))
+
+
+def tvlbm_batch_run(h, n_inst: int, max_steps: int, tol: float, k_interval: int = 100):
+    steps = (ctypes.c_int64 * n_inst)()
+    r = (ctypes.c_double * n_inst)()
+    rc = lib().tvlbm_batch_run(h, int(max_steps), float(tol), int(k_interval), steps, r)
+    if rc not in (TVLBM_OK, TVLBM_ENOTCONVERGED):
+        raise TvlbmError(rc, "batch run")
+    return rc == TVLBM_OK, np.array(steps[:]), np.array(r[:])
+
+
+def tvlbm_batch_fields(h, out):
+    _check(lib().tvlbm_batch_fields(h, _ptr(out)))
+
+
+def tvlbm_batch_set_shape(h, max_nx: int, width: int, rows: int):
+    _check(lib().tvlbm_batch_set_shape(h, int(max_nx), int(width), int(rows)))
+
+
+class BatchSolver:
+    """Many walled channels (periodic in x) solved together on one GPU.
+
+    instances: list of dicts with nx, ny, tau, and optionally u_bot, T_bot,
+    u_top, T_top (bottom wall velocity/temperature, top wall ...)."""
+
+    def __init__(self, instances, n_gh: int = 4, dtype: str = "f32", cfl: float = 0.9,
+                 compensated: bool = True, device=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device or "cuda:0")
+        self.n = len(instances)
+        self.q = n_gh * n_gh
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        arr = (tvlbm_inst * self.n)()
+        for k, d in enumerate(instances):
+            arr[k].nx, arr[k].ny = int(d["nx"]), int(d["ny"])
+            arr[k].tau = float(d["tau"])
+            arr[k].wall_lo_ux = float(d.get("u_bot", 0.0))
+            arr[k].wall_lo_T = float(d.get("T_bot", 1.0))
+            arr[k].wall_hi_ux = float(d.get("u_top", 0.0))
+            arr[k].wall_hi_T = float(d.get("T_top", 1.0))
+        self._arr = arr
+        self.shapes = [(int(d["nx"]), int(d["ny"])) for d in instances]
+        self.fld_off = np.concatenate([[0], np.cumsum([4 * nx * ny for nx, ny in self.shapes])])
+        desc = tvlbm_batch_desc()
+        desc.n_gh = n_gh
+        desc.eq_order = LATTICE_ORDER[n_gh]
+        desc.dtype = TVLBM_F32 if dtype == "f32" else TVLBM_F64
+        desc.compensated = int(compensated)
+        desc.cfl = cfl
+        desc.cfl_norm = TVLBM_CFL_EUCLID
+        desc.n_inst = self.n
+        desc.inst = ctypes.cast(arr, ctypes.POINTER(tvlbm_inst))
+        pop, fld = tvlbm_batch_sizes(desc)
+        self.pop_elems, self.field_elems = pop, fld
+        self.arena_a = torch.zeros(pop, dtype=self.tdtype, device=self.device)
+        self.arena_b = torch.zeros(pop, dtype=self.tdtype, device=self.device)
+        self.stream = torch.cuda.Stream(self.device)
+        desc.arena_a = self.arena_a.data_ptr()
+        desc.arena_b = self.arena_b.data_ptr()
+        desc.stream = self.stream.cuda_stream
+        self.desc = desc
+        torch.cuda.synchronize()
+        self.h = tvlbm_batch_init(desc)
+
+    def close(self):
+        if getattr(self, "h", None):
+            tvlbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fields(self, fields):
+        """fields: list of (rho, ux, uy, T) per instance (arrays [ny][nx] or
+        scalars), or one packed array of length field_elems."""
+        if isinstance(fields, (list, tuple)):
+            parts = []
+            for (nx, ny), f in zip(self.shapes, fields):
+                parts.append(np.stack([np.broadcast_to(np.asarray(a, dtype=np.float64), (ny, nx))
+                                       for a in f]).ravel())
+            packed = np.concatenate(parts)
+        else:
+            packed = np.asarray(fields, dtype=np.float64).ravel()
+        t = self.torch.as_tensor(packed, dtype=self.tdtype).to(self.device)
+        self.torch.cuda.synchronize()
+        tvlbm_batch_set_fields(self.h, t)
+        self.stream.synchronize()
+
+    def set_fields_device(self, packed):
+        """packed: device tensor of field_elems values in the solver dtype."""
+        self.torch.cuda.synchronize()
+        tvlbm_batch_set_fields(self.h, packed)
+        self.stream.synchronize()
+
+    def set_shape(self, max_nx: int, width: int, rows: int):
+        tvlbm_batch_set_shape(self.h, max_nx, width, rows)
+
+    def run(self, max_steps: int, tol: float = 1e-8, k_interval: int = 100):
+        return tvlbm_batch_run(self.h, self.n, max_steps, tol, k_interval)
+
+    def fields_packed(self):
+        out = self.torch.empty(self.field_elems, dtype=self.tdtype, device=self.device)
+        tvlbm_batch_fields(self.h, out)
+        return out
+
+    def fields(self):
+        flat = self.fields_packed().double().cpu().numpy()
+        return [flat[self.fld_off[k]:self.fld_off[k + 1]].reshape(4, ny, nx)
+                for k, (nx, ny) in enumerate(self.shapes)]

@@ -15,16 +15,17 @@ def rel_inf(a, b) -> float:
 
 
 def make_pair(nx, ny, n=4, dtype="f64", tau=0.8, walls=False, wall_lo=(0.0, 1.0),
-              wall_hi=(0.0, 1.0), collide=True, cfl=0.9, cfl_norm=0, compensated=True, variant=0):
+              wall_hi=(0.0, 1.0), collide=True, cfl=0.9, cfl_norm=0, compensated=True, variant=0,
+              dy=None):
     """A GPU solver and an oracle grid with identical parameters."""
     s = Solver(nx, ny, n_gh=n, dtype=dtype, tau=tau, walls=walls, wall_lo=wall_lo,
                wall_hi=wall_hi, collide=collide, cfl=cfl, cfl_norm=cfl_norm,
-               compensated=compensated)
+               compensated=compensated, dy=dy)
     if variant:
         s.set_variant(variant)
     lat = orc.OracleLattice(n, LATTICE_ORDER[n], cfl=cfl, cfl_norm=cfl_norm)
     g = orc.OracleGrid(lat, nx, ny, tau=tau, collide=collide, walls=walls, wall_lo=wall_lo,
-                       wall_hi=wall_hi)
+                       wall_hi=wall_hi, dy=dy)
     return s, g
 
 

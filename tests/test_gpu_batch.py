@@ -1,0 +1,93 @@
+"""Batched steady solves: every instance of a batch must equal the same
+instance solved alone through the single-instance path (bitwise: the same
+per-cell arithmetic runs in both), and match the FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_common import rel_inf, to_np  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+from paper_1004_5059_amd import inputs  # noqa: E402
+from paper_1004_5059_amd.tvlbm import BatchSolver, Solver  # noqa: E402
+
+INST = [
+    dict(nx=16, ny=32, tau=0.6, u_top=0.03, T_top=1.05),
+    dict(nx=24, ny=48, tau=1.1, u_top=0.07, T_top=1.18),
+    dict(nx=40, ny=80, tau=0.8, u_top=0.0, T_top=1.1),
+    dict(nx=64, ny=128, tau=0.7, u_top=0.05, T_top=1.0),
+    dict(nx=100, ny=20, tau=0.9, u_top=0.02, T_top=1.02),
+]
+
+
+def _single(d, dtype, steps):
+    s = Solver(d["nx"], d["ny"], n_gh=4, dtype=dtype, tau=d["tau"], walls=True,
+               wall_lo=(0.0, 1.0), wall_hi=(d["u_top"], d["T_top"]))
+    s.set_fields(*inputs.uniform_fields(d["nx"], d["ny"]))
+    s.step(steps)
+    f = to_np(s.moments()[0])
+    s.close()
+    return f
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_equals_single_instance_runs(dtype):
+    b = BatchSolver(INST, dtype=dtype)
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in INST])
+    ok, steps, r = b.run(max_steps=200, tol=0.0, k_interval=100)
+    assert not ok and np.all(steps == 200)
+    out = b.fields()
+    for d, f in zip(INST, out):
+        assert np.array_equal(f, _single(d, dtype, 200)), d
+    b.close()
+
+
+def test_batch_shapes_do_not_change_results():
+    res = []
+    for shape in [None, (128, 16, 4), (128, 32, 16), (128, 64, 1)]:
+        b = BatchSolver(INST, dtype="f32")
+        if shape:
+            b.set_shape(*shape)
+        b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in INST])
+        b.run(max_steps=100, tol=0.0, k_interval=50)
+        res.append(b.fields())
+        b.close()
+    for r in res[1:]:
+        for a, c in zip(r, res[0]):
+            assert np.array_equal(a, c)
+
+
+def test_batch_against_oracle_fp64():
+    inst = INST[:3]
+    b = BatchSolver(inst, dtype="f64")
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in inst])
+    b.run(max_steps=60, tol=0.0, k_interval=20)
+    out = b.fields()
+    lat = orc.OracleLattice(4, 3)
+    for d, f in zip(inst, out):
+        g = orc.OracleGrid(lat, d["nx"], d["ny"], tau=d["tau"], walls=True, wall_lo=(0.0, 1.0),
+                           wall_hi=(d["u_top"], d["T_top"]))
+        ref = g.fields(g.run(g.set_fields(*inputs.uniform_fields(d["nx"], d["ny"])), 60))
+        assert rel_inf(f[0], ref[0]) <= 1e-12 and rel_inf(f[3], ref[3]) <= 1e-12
+        assert np.max(np.abs(f[1] - ref[1])) <= 1e-12 * max(1.0, np.max(np.abs(ref[1])))
+
+
+def test_batch_retires_converged_instances_like_single_solves():
+    inst = [dict(nx=16, ny=32, tau=0.9, u_top=0.04, T_top=1.1),
+            dict(nx=24, ny=48, tau=0.6, u_top=0.02, T_top=1.05)]
+    b = BatchSolver(inst, dtype="f32")
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in inst])
+    ok, steps, r = b.run(max_steps=400000, tol=1e-8, k_interval=100)
+    assert ok and np.all(r < 1e-8)
+    out = b.fields()
+    for d, f, st in zip(inst, out, steps):
+        s = Solver(d["nx"], d["ny"], n_gh=4, dtype="f32", tau=d["tau"], walls=True,
+                   wall_lo=(0.0, 1.0), wall_hi=(d["u_top"], d["T_top"]))
+        s.set_fields(*inputs.uniform_fields(d["nx"], d["ny"]))
+        conv, n, rr = s.solve(400000, 1e-8, 100)
+        assert conv and n == st
+        assert np.array_equal(to_np(s.moments()[0]), f)
+        s.close()
+    assert steps[0] != steps[1]
+    b.close()

@@ -1,0 +1,71 @@
+"""Bounded thermal flow on the 512 x 256 channel with 2:1 refined bands of
+16 coarse rows at each wall (288 rows), D2Q16, FP32, tau 0.7, bottom wall at
+rest with T = 1, top wall u = 0.05, T = 1.1, run to residual 1e-8.
+
+Checks at full size: sampled cells against the oracle after a few steps (the
+oracle is run on the full channel height and a periodic strip of columns
+around each sample), total mass conserved, convergence, and the steady
+profile against the closed-form thermal Couette solution of the
+Navier-Stokes-Fourier limit (u = U y/H, T = T0 + dT y/H + U^2/(2 c_P)
+(y/H)(1 - y/H), c_P = 2).  The overlap remap is first-order upwind, so its
+numerical viscosity differs between the fine and coarse rows and bends the
+profile; the closed-form bound is set accordingly and the deviation is
+printed."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_common import to_np  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+from paper_1004_5059_amd import inputs  # noqa: E402
+from paper_1004_5059_amd.tvlbm import Solver  # noqa: E402
+
+NX = 512
+DY = inputs.refined_wall_rows(h=256, band=16, ratio=2)
+WALLS = dict(walls=True, wall_lo=(0.0, 1.0), wall_hi=(0.05, 1.1))
+
+
+def test_c2_sampled_cells_against_oracle():
+    K = 12
+    s = Solver(NX, len(DY), n_gh=4, dtype="f32", tau=0.7, dy=DY, **WALLS)
+    fields = inputs.shear_wave_fields(NX, len(DY), eps=0.02)
+    noise = inputs.population_noise(16, len(DY), NX, amp=1e-4, seed=6)
+    s.set_fields(*fields, noise)
+    s.step(K)
+    f = s.populations().cpu().numpy()
+    lat = orc.OracleLattice(4, 3)
+    h = K + 2
+    W = 2 * h + 1
+    g = orc.OracleGrid(lat, W, len(DY), tau=0.7, dy=DY, **WALLS)
+    for ci in (0, 255, 511):
+        ii = np.arange(ci - h, ci + h + 1) % NX
+        win = [a[:, ii] for a in fields]
+        fr = g.run(g.set_fields(*win, noise[:, :, ii]), K)
+        assert np.max(np.abs(f[:, :, ci] - fr[:, :, h])) / np.max(np.abs(fr)) <= 1e-5, ci
+    s.close()
+
+
+def test_c2_steady_thermal_couette():
+    s = Solver(NX, len(DY), n_gh=4, dtype="f32", tau=0.7, dy=DY, **WALLS)
+    s.set_fields(*inputs.uniform_fields(NX, len(DY)))
+    m0 = s.moments()[1][0]
+    conv, steps, r = s.solve(2_000_000, 1e-8, 100)
+    fld, tot = s.moments()
+    assert conv, (steps, r)
+    assert abs(tot[0] - m0) / m0 <= 1e-6
+    q = to_np(fld)
+    yb = np.concatenate([[0.0], np.cumsum(DY)])
+    yc = 0.5 * (yb[1:] + yb[:-1]) / yb[-1]
+    u = q[1].mean(axis=1)
+    T = q[3].mean(axis=1)
+    assert np.max(np.abs(q[1] - u[:, None])) < 1e-6  # x-invariant
+    ucf = 0.05 * yc
+    Tcf = 1.0 + 0.1 * yc + 0.05 ** 2 / 4.0 * yc * (1 - yc)
+    eu = np.max(np.abs(u - ucf)) / 0.05
+    eT = np.max(np.abs(T - Tcf)) / 0.1
+    print(f"C2 steady after {steps} steps (r={r:.2e}): max|u-u_cf|/U = {eu:.4f}, "
+          f"max|T-T_cf|/dT = {eT:.4f}, slip u(0)={u[0]:.5f} u(H)={u[-1]:.5f}")
+    assert eu <= 0.08 and eT <= 0.08
+    s.close()

@@ -214,3 +214,42 @@ def test_residual_matches_field_definition():
     expect = orc.residual(q1, q0, 40)
     assert abs(r - expect) <= 1e-10 * expect
     s.close()
+
+
+@pytest.mark.parametrize("n,dtype,tol,walls", [(4, "f64", 1e-12, True), (4, "f32", 1e-5, True),
+                                               (6, "f64", 1e-12, True), (4, "f64", 1e-12, False)])
+def test_refined_rows_parity(n, dtype, tol, walls):
+    """Rows refined 2:1 next to each wall (rectangular cells), 80 steps."""
+    dy = inputs.refined_wall_rows(h=24, band=4) if walls else \
+        np.array([0.5, 0.5, 1.0, 1.0, 0.25, 0.25, 0.5, 1.0, 1.0, 0.5, 1.0, 1.0])
+    ny, nx = len(dy), 72
+    kw = dict(walls=walls, wall_lo=(0.0, 1.0), wall_hi=(0.05, 1.1))
+    s, g = make_pair(nx, ny, n=n, dtype=dtype, tau=0.7, dy=dy, **kw)
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    noise = inputs.population_noise(n * n, ny, nx, amp=1e-4, seed=4)
+    s.set_fields(*fields, noise)
+    f_ref = g.set_fields(*fields, noise)
+    t0 = g.totals(f_ref)
+    s.step(80)
+    f_ref = g.run(f_ref, 80)
+    tot = _compare_state(s, g, f_ref, tol)
+    cons = 1e-13 if dtype == "f64" else 1e-6
+    assert abs(tot[0] - t0[0]) / t0[0] <= cons
+    np.testing.assert_allclose(tot, g.totals(f_ref), rtol=1e-12 if dtype == "f64" else 1e-6,
+                               atol=1e-10 * t0[0])
+
+
+def test_refined_rows_uniform_heights_match_uniform_kernel():
+    """Unit row heights through the row-table kernel reproduce the marching
+    kernel (same arithmetic up to rounding order)."""
+    nx, ny = 64, 20
+    kw = dict(walls=True, wall_hi=(0.04, 1.08))
+    s1, _ = make_pair(nx, ny, n=4, dtype="f64", tau=0.75, **kw)
+    s2, _ = make_pair(nx, ny, n=4, dtype="f64", tau=0.75, dy=np.ones(ny), **kw)
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    for s in (s1, s2):
+        s.set_fields(*fields)
+        s.step(50)
+    assert rel_inf(to_np(s1.populations()), to_np(s2.populations())) <= 1e-13
+    s1.close()
+    s2.close()
