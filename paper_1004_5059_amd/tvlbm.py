@@ -499,3 +499,147 @@ class BatchSolver:
         flat = self.fields_packed().double().cpu().numpy()
         return [flat[self.fld_off[k]:self.fld_off[k + 1]].reshape(4, ny, nx)
                 for k, (nx, ny) in enumerate(self.shapes)]
+
+
+# ----------------------------------------------------- warm-start network --
+class tvnet_desc(ctypes.Structure):
+    _fields_ = [
+        ("c_in", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("c_out", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("cols", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+def _tvnet_lib():
+    L = lib()
+    if not hasattr(L, "_tvnet_sig"):
+        sig = {
+            "tvnet_init": [ctypes.POINTER(tvnet_desc), ctypes.POINTER(_vp)],
+            "tvnet_destroy": [_vp],
+            "tvnet_num_params": [_vp, _i64p],
+            "tvnet_set_params": [_vp, _fp],
+            "tvnet_get_params": [_vp, _fp],
+            "tvnet_forward": [_vp, _vp, _vp, ctypes.c_int32],
+            "tvnet_backward": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _dp],
+            "tvnet_get_grads": [_vp, _fp],
+            "tvnet_adam_step": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_int32],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L._tvnet_sig = True
+    return L
+
+
+def tvnet_init(desc: tvnet_desc):
+    h = _vp()
+    _check(_tvnet_lib().tvnet_init(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def tvnet_destroy(h):
+    _check(_tvnet_lib().tvnet_destroy(h))
+
+
+def tvnet_num_params(h) -> int:
+    n = ctypes.c_int64()
+    _check(_tvnet_lib().tvnet_num_params(h, ctypes.byref(n)))
+    return n.value
+
+
+def tvnet_set_params(h, params: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_tvnet_lib().tvnet_set_params(h, p.ctypes.data_as(_fp)))
+
+
+def tvnet_get_params(h, n: int) -> np.ndarray:
+    p = np.zeros(n, dtype=np.float32)
+    _check(_tvnet_lib().tvnet_get_params(h, p.ctypes.data_as(_fp)))
+    return p
+
+
+def tvnet_forward(h, x, y, batch: int):
+    _check(_tvnet_lib().tvnet_forward(h, _ptr(x), _ptr(y), int(batch)))
+
+
+def tvnet_backward(h, target, mask, batch: int, mask_sum: float) -> float:
+    loss = ctypes.c_double()
+    _check(_tvnet_lib().tvnet_backward(h, _ptr(target), _ptr(mask), int(batch), float(mask_sum),
+                                       ctypes.byref(loss)))
+    return loss.value
+
+
+def tvnet_get_grads(h, n: int) -> np.ndarray:
+    g = np.zeros(n, dtype=np.float32)
+    _check(_tvnet_lib().tvnet_get_grads(h, g.ctypes.data_as(_fp)))
+    return g
+
+
+def tvnet_adam_step(h, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, t: int = 1):
+    _check(_tvnet_lib().tvnet_adam_step(h, lr, b1, b2, eps, int(t)))
+
+
+class TvNet:
+    """The warm-start network on the GPU; tensors are torch device tensors,
+    channels last."""
+
+    def __init__(self, c_in: int, height: int, cols: int, max_batch: int, c_out: int = 4,
+                 device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device or "cuda:0")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        d = tvnet_desc()
+        d.c_in, d.width, d.c_out = c_in, 32, c_out
+        d.height, d.cols, d.max_batch = height, cols, max_batch
+        d.stream = self.stream.cuda_stream
+        self.c_in, self.c_out, self.H, self.W, self.max_batch = c_in, c_out, height, cols, max_batch
+        self.h = tvnet_init(d)
+        self.n_params = tvnet_num_params(self.h)
+        self.t = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            tvnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        tvnet_set_params(self.h, flat)
+        self.t = 0
+
+    def params(self):
+        return tvnet_get_params(self.h, self.n_params)
+
+    def forward(self, x):
+        B = x.shape[0]
+        y = self.torch.empty((B, self.H, self.W, self.c_out), dtype=self.torch.float32, device=self.device)
+        tvnet_forward(self.h, x.contiguous(), y, B)
+        return y
+
+    def backward(self, target, mask) -> float:
+        B = target.shape[0]
+        ms = float(mask.sum().item())
+        return tvnet_backward(self.h, target.contiguous(), mask.contiguous(), B, ms)
+
+    def grads(self):
+        return tvnet_get_grads(self.h, self.n_params)
+
+    def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        self.t += 1
+        tvnet_adam_step(self.h, lr, b1, b2, eps, self.t)
