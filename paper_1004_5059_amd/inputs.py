@@ -82,10 +82,11 @@ def uniform_fields(nx: int, ny: int, rho: float = 1.0, T: float = 1.0):
     return rho * one, 0.0 * one, 0.0 * one, T * one
 
 
-def couette_instances(n: int, seed: int = 2026):
-    """List of dicts: nx, ny, tau, u_top, T_bot, T_top (bottom wall at rest)."""
+def couette_instances(n: int, seed: int = 2026, sizes=None):
+    """List of dicts: nx, ny, tau, u_top, T_bot, T_top (bottom wall at rest).
+    sizes: the N_y values to draw from (default 32, 48, ..., 256)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    sizes = np.arange(32, 257, 16)
+    sizes = np.arange(32, 257, 16) if sizes is None else np.asarray(sizes)
     out = []
     for _ in range(n):
         ny = int(rng.choice(sizes))
