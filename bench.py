@@ -72,6 +72,29 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
     }
 
 
+def copy_ceiling(mib: int = 1024, reps: int = 10):
+    """Device-to-device copy of a buffer larger than the MALL: the achievable
+    HBM bandwidth ceiling (bytes read + bytes written per second)."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "gbs": 2 * n * 4 / (ms / 1e3) / 1e9}
+
+
 def cpu_baseline(size: int, target_s: float = 12.0):
     """The FP64 oracle, as it stands, on this host's cores: a bounded sample
     (a few steps of the same 1024^2 D2Q16 workload)."""
@@ -114,6 +137,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2q36", action="store_true")
+    ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 run")
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the TVLBM path here is single-GPU "
@@ -122,6 +147,8 @@ def main():
 
     r16 = run_lattice(4, args.size, args.steps, args.warmup, args.variant)
     r36 = None if args.no_d2q36 else run_lattice(6, args.size, args.steps, args.warmup, args.variant)
+    big = None if args.no_4096 else run_lattice(4, 4096, max(20, args.steps // 10), 5, args.variant)
+    cp = None if args.no_copy else copy_ceiling()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.size)
     achieved = r16["achieved_gbs"]
     out = {
@@ -150,6 +177,10 @@ def main():
             "achieved_gbs": round(r36["achieved_gbs"], 1),
             "frac": round(r36["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": r36["variant"]},
         "autotune_ms_per_step": r16["tune_ms"],
+        "d2q16_4096": None if big is None else {
+            "mlups": round(big["mlups"], 1), "achieved_gbs": round(big["achieved_gbs"], 1),
+            "frac": round(big["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": big["variant"]},
+        "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
     }
     print(json.dumps(out), flush=True)
 

@@ -98,8 +98,8 @@ double ovl(double a0, double a1, double b0, double b1) {
 }
 
 struct TapD {
-  int src[3];
-  double w[3];
+  int src[4];
+  double w[4];
   double glo, ghi;
 };
 struct IncD {
@@ -111,9 +111,12 @@ struct IncD {
 // shifted source interval [y_j + s, y_{j+1} + s] against target row k, with
 // periodic images when there are no walls, the wall-emission intervals
 // [0, s] (bottom, s > 0) and [H - |s|, H] (top, s < 0), and the lengths of
-// shifted rows lying beyond a wall.  Returns false if a target row needs more
-// than three source rows or more than four rows cross a wall.
-bool build_row_tables(const HostLattice& H, int ny, const double* dy, bool walls,
+// shifted rows lying beyond a wall.  `p` are the displacements as the kernels
+// use them (rounded to the dtype's unit-interval grid), so that on dyadic row
+// heights every overlap is exact in the working precision and each source
+// row's mass is redistributed exactly.  Returns false if a target row needs
+// more than four source rows or more than four rows cross a wall.
+bool build_row_tables(const HostLattice& H, const double* p, int ny, const double* dy, bool walls,
                       std::vector<TapD>& taps, std::vector<IncD>& inc, std::vector<int32_t>& flag) {
   const int n = H.n;
   std::vector<double> y(ny + 1, 0.0);
@@ -123,7 +126,7 @@ bool build_row_tables(const HostLattice& H, int ny, const double* dy, bool walls
   inc.assign(n, IncD{});
   flag.assign(ny, 0);
   for (int b = 0; b < n; ++b) {
-    const double s = (H.x[b] < 0 ? -1.0 : 1.0) * H.p[b];
+    const double s = (H.x[b] < 0 ? -1.0 : 1.0) * p[b];
     for (int k = 0; k < ny; ++k) {
       TapD& T = taps[(size_t)b * ny + k];
       int cnt = 0;
@@ -132,13 +135,13 @@ bool build_row_tables(const HostLattice& H, int ny, const double* dy, bool walls
         double len = ovl(a0, a1, 0.0, dy[k]);
         if (!walls) len += ovl(a0 - Hy, a1 - Hy, 0.0, dy[k]) + ovl(a0 + Hy, a1 + Hy, 0.0, dy[k]);
         if (len > 0.0) {
-          if (cnt == 3) return false;
+          if (cnt == 4) return false;
           T.src[cnt] = j;
           T.w[cnt] = len / dy[k];
           ++cnt;
         }
       }
-      for (int t = cnt; t < 3; ++t) { T.src[t] = k; T.w[t] = 0.0; }
+      for (int t = cnt; t < 4; ++t) { T.src[t] = k; T.w[t] = 0.0; }
       T.glo = T.ghi = 0.0;
       if (walls) {
         if (s > 0.0) T.glo = ovl(-y[k], s - y[k], 0.0, dy[k]) / dy[k];
@@ -172,7 +175,7 @@ int upload_rows(tvlbm_ctx* c, const std::vector<TapD>& taps, const std::vector<I
   std::vector<RowTap<R>> t(taps.size());
   for (size_t k = 0; k < taps.size(); ++k) {
     std::memset(&t[k], 0, sizeof t[k]);
-    for (int q = 0; q < 3; ++q) { t[k].src[q] = taps[k].src[q]; t[k].w[q] = (R)taps[k].w[q]; }
+    for (int q = 0; q < 4; ++q) { t[k].src[q] = taps[k].src[q]; t[k].w[q] = (R)taps[k].w[q]; }
     t[k].glo = (R)taps[k].glo;
     t[k].ghi = (R)taps[k].ghi;
   }
@@ -242,6 +245,40 @@ static void fill_lat(const HostLattice& H, Lat<R>& L) {
 // equal to the displacement p_b.  In deviation form g_l - w_l =
 // kap_l + phi_l m with phi_l = feqw_l / Z and kap_l = C phi_l - w_l.
 template <typename R>
+static double pull_frac(const HostLattice& H, int a) {
+  const double ulp = std::is_same<R, float>::value ? 0x1p-24 : 0x1p-53;
+  return std::nearbyint(H.p[a] / ulp) * ulp;
+}
+
+// Wall coefficients of the emitting populations (one wall) rounded to R so
+// that the emitted deviation mass equals the incident one in exact
+// arithmetic of the rounded values: sum_l p_l kap_l = 0 and
+// sum_l p_l phi_l = 1, p_l the displacement of population l across the wall.
+// The rounding residual is absorbed by the last emitting population.
+template <typename R>
+static void balance_wall(const std::vector<int>& ls, const std::vector<double>& pl,
+                         const double* kap, const double* phi, R* kap_out, R* phi_out) {
+  double sk = 0.0, sp = 0.0;
+  for (size_t t = 0; t + 1 < ls.size(); ++t) {
+    kap_out[ls[t]] = (R)kap[ls[t]];
+    phi_out[ls[t]] = (R)phi[ls[t]];
+    sk += pl[t] * (double)kap_out[ls[t]];
+    sp += pl[t] * (double)phi_out[ls[t]];
+  }
+  const int last = ls.back();
+  kap_out[last] = (R)(-sk / pl.back());
+  phi_out[last] = (R)((1.0 - sp) / pl.back());
+}
+
+// Per-instance constants: relaxation and the wall ghost coefficients.
+// Bottom wall (y = 0): incident populations move down (x_b < 0); the
+// re-emitted ones (x_b > 0) carry ghost values
+//   g_l = (C + m) feqw_l / Z,  Z = sum_{x_b>0} p_b feqw_l,
+//   C = sum_{x_b<0} p_b w_l  (rest-state part of the incident mass),
+// i.e. the flux-weighted wall Maxwellian of eq.(IMPOSITION) with |c.n| dt
+// equal to the displacement p_b.  In deviation form g_l - w_l =
+// kap_l + phi_l m with phi_l = feqw_l / Z and kap_l = C phi_l - w_l.
+template <typename R>
 static void fill_inst(const HostLattice& H, double tau, int collide, int walls, double ulo,
                       double Tlo, double uhi, double Thi, int nx, int ny, int64_t ld, int64_t off,
                       int64_t fld, Inst<R>& P) {
@@ -263,26 +300,34 @@ static void fill_inst(const HostLattice& H, double tau, int collide, int walls, 
     host_feq(H, 1.0, uhi, 0.0, Thi, fh);
     double zlo = 0.0, zhi = 0.0, clo = 0.0, chi = 0.0;
     for (int b = 0; b < n; ++b) {
+      const double pb = pull_frac<R>(H, b);
       for (int a = 0; a < n; ++a) {
         const int l = a * n + b;
-        if (H.x[b] > 0) { zlo += H.p[b] * fl[l]; chi += H.p[b] * H.w[l]; }
-        if (H.x[b] < 0) { zhi += H.p[b] * fh[l]; clo += H.p[b] * H.w[l]; }
+        if (H.x[b] > 0) { zlo += pb * fl[l]; chi += pb * H.w[l]; }
+        if (H.x[b] < 0) { zhi += pb * fh[l]; clo += pb * H.w[l]; }
       }
     }
+    double klo[36] = {0}, plo[36] = {0}, khi[36] = {0}, phi[36] = {0};
+    std::vector<int> llo, lhi;
+    std::vector<double> plo_w, phi_w;
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) {
         const int l = a * n + b;
         if (H.x[b] > 0) {
-          const double phi = fl[l] / zlo;
-          P.phi_lo[l] = (R)phi;
-          P.kap_lo[l] = (R)(clo * phi - H.w[l]);
+          plo[l] = fl[l] / zlo;
+          klo[l] = clo * plo[l] - H.w[l];
+          llo.push_back(l);
+          plo_w.push_back(pull_frac<R>(H, b));
         }
         if (H.x[b] < 0) {
-          const double phi = fh[l] / zhi;
-          P.phi_hi[l] = (R)phi;
-          P.kap_hi[l] = (R)(chi * phi - H.w[l]);
+          phi[l] = fh[l] / zhi;
+          khi[l] = chi * phi[l] - H.w[l];
+          lhi.push_back(l);
+          phi_w.push_back(pull_frac<R>(H, b));
         }
       }
+    balance_wall<R>(llo, plo_w, klo, plo, P.kap_lo, P.phi_lo);
+    balance_wall<R>(lhi, phi_w, khi, phi, P.kap_hi, P.phi_hi);
   }
 }
 
@@ -429,7 +474,9 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
     std::vector<TapD> taps;
     std::vector<IncD> inc;
     std::vector<int32_t> flag;
-    if (!build_row_tables(c->hl, d->ny, c->dyh.data(), walls != 0, taps, inc, flag)) {
+    double pr[8];
+    for (int q = 0; q < c->hl.n; ++q) pr[q] = c->f64 ? (double)c->latd.p[q] : (double)c->latf.p[q];
+    if (!build_row_tables(c->hl, pr, d->ny, c->dyh.data(), walls != 0, taps, inc, flag)) {
       tvlbm_destroy(c);
       return TVLBM_EUNSUPPORTED;
     }

@@ -67,14 +67,13 @@ struct Work {      // one wavefront's share of a batched step
 
 // Non-uniform rows (the rectangular meshes of Sec. III, uniform in x):
 // for y-node b and target row k, the pulled value is
-//   sum_t w[t] X_a(row src[t]) + glo * ghost_lo + ghi * ghost_hi,
+//   sum_{t<4} w[t] X_a(row src[t]) + glo * ghost_lo + ghi * ghost_hi,
 // where w = (overlap of the shifted source row with row k) / dy_k and the
 // ghost weights are the overlaps of the wall-emission intervals.
 template <typename R>
 struct RowTap {
-  int32_t src[3];
-  int32_t pad;
-  R w[3];
+  int32_t src[4];
+  R w[4];
   R glo, ghi;
 };
 // Rows whose shifted interval crosses a wall, per y-node b, with the length

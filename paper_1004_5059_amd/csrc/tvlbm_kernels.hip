@@ -404,16 +404,16 @@ __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& 
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const RowTap<R>& T = A.taps[b * ny + k];
-      RowOff o[3];
+      RowOff o[4];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) o[t] = row_off((uint32_t)T.src[t] * ld, ic, im, ip);
+      for (int t = 0; t < 4; ++t) o[t] = row_off((uint32_t)T.src[t] * ld, ic, im, ip);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         const int l = a * N + b;
         const uint32_t pl = (uint32_t)(l * plane);
         R acc = R(0);
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
+        for (int t = 0; t < 4; ++t)
           if (T.w[t] != R(0)) acc = fmaR(T.w[t], xpull<R, N>(L, s, pl, a, o[t]), acc);
         if ((flag & 1) && T.glo != R(0))
           acc = fmaR(T.glo, ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], lo_c, lo_m, lo_p), acc);
