@@ -184,10 +184,25 @@ __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& 
   }
 }
 
+// Ghost value of an emitting population at the wall it leaves: sg > 0
+// (moving up) is emitted by the bottom wall, sg < 0 by the top wall.
+template <typename R, int N>
+__device__ __forceinline__ R ghost_of(const Lat<R>& L, const Inst<R>& P, int a, int b, R m_c, R m_m,
+                                      R m_p) {
+  const int l = a * N + b;
+  return node_sign<N>(b) > 0 ? ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], m_c, m_m, m_p)
+                             : ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], m_c, m_m, m_p);
+}
+
 // Everything one lane does for one row j: pull, moments, equilibrium,
-// collision, store (or the auxiliary outputs).  GHOST_HI: row j is the last
-// row of a walled channel and the downward populations pull the top ghost.
-template <typename R, int N, int ORD, bool COMP, int MODE, bool GHOST_HI>
+// collision, store (or the auxiliary outputs).  The lane marches in
+// direction DIR (+1: increasing j, -1: decreasing j).  A population whose
+// upstream row is the row visited before ("lead": sign(x_b) == DIR) pulls
+// rows j (1-p) and j-DIR (p), the latter kept in hp from the previous row;
+// the others ("trail") pull rows j and j+DIR, loading j+DIR now and keeping
+// it for the next row.  GHOST: row j+DIR lies beyond a wall; the trail
+// populations pull that wall's ghost (m_* is its incident mass).
+template <typename R, int N, int ORD, bool COMP, int MODE, int DIR, bool GHOST>
 __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& P,
                                           rsrc_t s, rsrc_t dst, R (&hp)[N * N], int j,
                                           int i, int ic, int im, int ip, bool active,
@@ -196,20 +211,23 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
   const int64_t plane = P.plane;
-  const uint32_t rj = (uint32_t)j * (uint32_t)P.ld;
+  const uint32_t ld = (uint32_t)P.ld;
+  const uint32_t rj = (uint32_t)j * ld;
   R d[Q];
   if (ident) {
 #pragma unroll
     for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, rj + (uint32_t)ic, (uint32_t)(l * plane));
   } else {
     const RowOff oj = row_off(rj, ic, im, ip);
-    const uint32_t rn = (j + 1 == ny) ? 0u : rj + (uint32_t)P.ld;
-    const RowOff on = row_off(rn, ic, im, ip);
+    int jn = j + DIR;
+    jn = jn < 0 ? ny - 1 : (jn >= ny ? 0 : jn);  // periodic; walls use GHOST
+    const RowOff on = row_off((uint32_t)jn * ld, ic, im, ip);
     R m_c = R(0), m_m = R(0), m_p = R(0);
-    if constexpr (GHOST_HI) {
-      m_c = wall_mass<R, N>(L, s, plane, rj, ic, nx, +1);
-      m_m = wall_mass<R, N>(L, s, plane, rj, im, nx, +1);
-      m_p = wall_mass<R, N>(L, s, plane, rj, ip, nx, +1);
+    if constexpr (GHOST) {
+      // incident mass through the wall next to row j (top for DIR > 0)
+      m_c = wall_mass<R, N>(L, s, plane, rj, ic, nx, DIR);
+      m_m = wall_mass<R, N>(L, s, plane, rj, im, nx, DIR);
+      m_p = wall_mass<R, N>(L, s, plane, rj, ip, nx, DIR);
     }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
@@ -218,14 +236,14 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
         const int l = a * N + b;
         const int sg = node_sign<N>(b);
         const uint32_t pl = (uint32_t)(l * plane);
-        if (sg > 0) {  // moving up: rows j (1-p) and j-1 (p)
+        if (sg == DIR) {  // lead
           R hn = xpull<R, N>(L, s, pl, a, oj);
           d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
           hp[l] = hn;
-        } else if (sg < 0) {  // moving down: rows j (1-p) and j+1 (p)
+        } else if (sg == -DIR) {  // trail
           R hn;
-          if constexpr (GHOST_HI)
-            hn = ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], m_c, m_m, m_p);
+          if constexpr (GHOST)
+            hn = ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p);
           else
             hn = xpull<R, N>(L, s, pl, a, on);
           d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
@@ -240,14 +258,16 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
   cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, j, i, active, 1.0, tot, bad);
 }
 
-template <typename R, int N, int ORD, bool COMP, int MODE>
-__device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>& P, int i,
-                                           bool active, int j0, int j1, double (&tot)[4],
-                                           int& bad) {
+// One lane's segment of rows [j0, j1), marched in direction DIR.
+template <typename R, int N, int ORD, bool COMP, int MODE, int DIR>
+__device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& P, int i,
+                                          bool active, int j0, int j1, double (&tot)[4],
+                                          int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
   const int64_t plane = P.plane;
+  const uint32_t ld = (uint32_t)P.ld;
   const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(R));
   const rsrc_t s = make_rsrc(A.src + P.off, bytes);
   const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
@@ -255,29 +275,38 @@ __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>&
   const int im = ic == 0 ? nx - 1 : ic - 1;
   const int ip = ic == nx - 1 ? 0 : ic + 1;
   const bool ident = (MODE == MODE_AUX) && (A.aux & AUX_IDENTITY);
+  const int jf = DIR > 0 ? j0 : j1 - 1;         // first row visited
+  const int jl = DIR > 0 ? j1 - 1 : j0;         // last row visited
+  // a wall lies before the first row / after the last row
+  const bool wall_first = P.walls && (DIR > 0 ? j0 == 0 : j1 == ny);
+  const bool wall_last = P.walls && (DIR > 0 ? j1 == ny : j0 == 0);
 
   R hp[Q];
   if (!ident) {
-    const bool ghost_lo = P.walls && j0 == 0;
+    // lead populations need the row before jf (or that wall's ghost);
+    // trail populations start from row jf itself.
     R m_c = R(0), m_m = R(0), m_p = R(0);
-    if (ghost_lo) {
-      m_c = wall_mass<R, N>(L, s, plane, 0u, ic, nx, -1);
-      m_m = wall_mass<R, N>(L, s, plane, 0u, im, nx, -1);
-      m_p = wall_mass<R, N>(L, s, plane, 0u, ip, nx, -1);
+    const uint32_t rw = (uint32_t)(DIR > 0 ? 0 : ny - 1) * ld;  // wall row
+    if (wall_first) {
+      m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, -DIR);
+      m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, -DIR);
+      m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, -DIR);
     }
-    const RowOff op = row_off((uint32_t)(j0 == 0 ? ny - 1 : j0 - 1) * (uint32_t)P.ld, ic, im, ip);
-    const RowOff oc = row_off((uint32_t)j0 * (uint32_t)P.ld, ic, im, ip);
+    int jb = jf - DIR;
+    jb = jb < 0 ? ny - 1 : (jb >= ny ? 0 : jb);
+    const RowOff ob = row_off((uint32_t)jb * ld, ic, im, ip);
+    const RowOff of = row_off((uint32_t)jf * ld, ic, im, ip);
 #pragma unroll
     for (int a = 0; a < N; ++a) {
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         const int l = a * N + b;
         const int sg = node_sign<N>(b);
-        if (sg > 0) {
-          hp[l] = ghost_lo ? ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], m_c, m_m, m_p)
-                           : xpull<R, N>(L, s, (uint32_t)(l * plane), a, op);
-        } else if (sg < 0) {
-          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, oc);
+        if (sg == DIR) {
+          hp[l] = wall_first ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p)
+                             : xpull<R, N>(L, s, (uint32_t)(l * plane), a, ob);
+        } else if (sg == -DIR) {
+          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, of);
         } else {
           hp[l] = R(0);
         }
@@ -285,15 +314,28 @@ __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>&
     }
   }
 
-  const int jmain = (P.walls && j1 == ny) ? j1 - 1 : j1;
-  for (int j = j0; j < jmain; ++j)
-    march_row<R, N, ORD, COMP, MODE, false>(A, P, s, dst, hp, j, i, ic, im, ip, active, ident, tot, bad);
-  if (jmain < j1) {
-    if (ident)
-      march_row<R, N, ORD, COMP, MODE, false>(A, P, s, dst, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
-    else
-      march_row<R, N, ORD, COMP, MODE, true>(A, P, s, dst, hp, jmain, i, ic, im, ip, active, ident, tot, bad);
-  }
+  const int nrow = j1 - j0;
+  const int nmain = (wall_last && !ident) ? nrow - 1 : nrow;
+  int j = jf;
+  for (int r = 0; r < nmain; ++r, j += DIR)
+    march_row<R, N, ORD, COMP, MODE, DIR, false>(A, P, s, dst, hp, j, i, ic, im, ip, active, ident,
+                                                 tot, bad);
+  if (nmain < nrow)
+    march_row<R, N, ORD, COMP, MODE, DIR, true>(A, P, s, dst, hp, jl, i, ic, im, ip, active, ident,
+                                                tot, bad);
+}
+
+// Segments alternate direction (group parity), so two neighbouring segments
+// touch their shared halo rows at the same time -- both at their start or
+// both at their end -- and the second read hits in L2.
+template <typename R, int N, int ORD, bool COMP, int MODE>
+__device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>& P, int i,
+                                           bool active, int j0, int j1, int group, double (&tot)[4],
+                                           int& bad) {
+  if (group & 1)
+    march_dir<R, N, ORD, COMP, MODE, -1>(A, P, i, active, j0, j1, tot, bad);
+  else
+    march_dir<R, N, ORD, COMP, MODE, +1>(A, P, i, active, j0, j1, tot, bad);
 }
 
 template <int MODE>
@@ -333,11 +375,12 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
   if (t < A.n_tiles) {
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int i = tx * W + (lane & (W - 1));
-    const int seg = ty * spb + wave * spw + lane / W;
+    const int group = ty * 4 + wave;  // wave-uniform segment group
+    const int seg = group * spw + lane / W;
     const int j0 = seg * A.rows;
     const int j1 = min(j0 + A.rows, A.inst.ny);
     if (j0 < A.inst.ny)
-      march_lane<R, N, ORD, COMP, MODE>(A, A.inst, i, i < A.inst.nx, j0, j1, tot, bad);
+      march_lane<R, N, ORD, COMP, MODE>(A, A.inst, i, i < A.inst.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
     if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
@@ -475,7 +518,8 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
     const int seg = it.seg0 + lane / W;
     const int j0 = seg * rows;
     const int j1 = min(j0 + rows, P.ny);
-    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE>(A, P, i, i < P.nx, j0, j1, tot, bad);
+    const int group = it.seg0 / (64 / W);
+    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
     if (bad) A.flag[0] = 1;
