@@ -22,12 +22,14 @@ using namespace tvlbm;
 namespace {
 
 struct Variant {
-  int width;  // columns per wavefront strip
-  int rows;   // rows per lane segment
+  int width;     // columns per wavefront strip
+  int rows;      // rows per lane segment
+  int prefetch;  // software-pipelined rows
 };
 // Launch shapes of the fused step; all compute identical results.
-const Variant kVariants[] = {{64, 4}, {64, 2}, {64, 8}, {64, 16}, {64, 1},
-                             {32, 4}, {32, 8}, {16, 8}, {16, 16}};
+const Variant kVariants[] = {{64, 4, 1}, {64, 2, 1}, {64, 8, 1}, {64, 16, 1}, {64, 4, 0},
+                             {64, 8, 0}, {32, 8, 1}, {32, 16, 1}, {16, 16, 1}, {64, 2, 0},
+                             {32, 8, 0}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -356,6 +358,7 @@ static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst
   A.inst = inst_of<R>(c);
   A.width = v.width;
   A.rows = v.rows;
+  A.prefetch = v.prefetch;
   A.aux = aux;
   A.tiles_x = g.tiles_x;
   A.n_tiles = g.n_tiles;

@@ -94,6 +94,7 @@ struct MarchArgs {
   int32_t width;          // columns per wavefront strip: 16, 32 or 64
   int32_t rows;           // rows per lane segment
   int32_t aux;            // AuxBits for MODE_AUX
+  int32_t prefetch;       // step kernel: software-pipelined rows
   int32_t tiles_x;        // strips across the grid (single-instance)
   int32_t n_tiles;        // workgroup tiles (single-instance)
   const R* src;           // deviations g^k (or f^0 with AUX_IDENTITY)

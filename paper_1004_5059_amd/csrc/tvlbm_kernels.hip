@@ -258,8 +258,54 @@ __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& 
   cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, j, i, active, 1.0, tot, bad);
 }
 
+// Software-pipelined rows: the raw loads of the next row (centre and
+// upstream column of every population) are issued before the current row
+// is computed, so a wavefront always has a row of loads in flight.
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void fetch_row(rsrc_t s, int64_t plane, uint32_t ld, int ny, int j, int ic,
+                                          int im, int ip, R (&c)[N * N], R (&nb)[N * N]) {
+  int jn = j + DIR;
+  jn = jn < 0 ? ny - 1 : (jn >= ny ? 0 : jn);
+  const uint32_t rj = (uint32_t)j * ld, rn = (uint32_t)jn * ld;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      const uint32_t row = (node_sign<N>(b) == -DIR) ? rn : rj;
+      const uint32_t pl = (uint32_t)(l * plane);
+      c[l] = bld<R>(s, row + (uint32_t)ic, pl);
+      const int sa = node_sign<N>(a);
+      nb[l] = sa > 0 ? bld<R>(s, row + (uint32_t)im, pl) : (sa < 0 ? bld<R>(s, row + (uint32_t)ip, pl) : R(0));
+    }
+  }
+}
+
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void pull_row(const Lat<R>& L, const R (&c)[N * N], const R (&nb)[N * N],
+                                         R (&hp)[N * N], R (&d)[N * N]) {
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      const R h = node_sign<N>(a) != 0 ? fmaR(L.qm[a], c[l], L.p[a] * nb[l]) : c[l];
+      const int sg = node_sign<N>(b);
+      if (sg == DIR) {
+        d[l] = fmaR(L.qm[b], h, L.p[b] * hp[l]);
+        hp[l] = h;
+      } else if (sg == -DIR) {
+        d[l] = fmaR(L.qm[b], hp[l], L.p[b] * h);
+        hp[l] = h;
+      } else {
+        d[l] = h;
+      }
+    }
+  }
+}
+
 // One lane's segment of rows [j0, j1), marched in direction DIR.
-template <typename R, int N, int ORD, bool COMP, int MODE, int DIR>
+template <typename R, int N, int ORD, bool COMP, int MODE, int DIR, bool PF>
 __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& P, int i,
                                           bool active, int j0, int j1, double (&tot)[4],
                                           int& bad) {
@@ -317,9 +363,23 @@ __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& 
   const int nrow = j1 - j0;
   const int nmain = (wall_last && !ident) ? nrow - 1 : nrow;
   int j = jf;
-  for (int r = 0; r < nmain; ++r, j += DIR)
-    march_row<R, N, ORD, COMP, MODE, DIR, false>(A, P, s, dst, hp, j, i, ic, im, ip, active, ident,
-                                                 tot, bad);
+  if constexpr (PF && MODE == MODE_STEP) {
+    R cc[Q], cn[Q];
+    if (nmain > 0) fetch_row<R, N, DIR>(s, plane, ld, ny, j, ic, im, ip, cc, cn);
+    for (int r = 0; r < nmain; ++r, j += DIR) {
+      R nc[Q], nn[Q];
+      if (r + 1 < nmain) fetch_row<R, N, DIR>(s, plane, ld, ny, j + DIR, ic, im, ip, nc, nn);
+      R d[Q];
+      pull_row<R, N, DIR>(L, cc, cn, hp, d);
+      cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, j, i, active, 1.0, tot, bad);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) { cc[l] = nc[l]; cn[l] = nn[l]; }
+    }
+  } else {
+    for (int r = 0; r < nmain; ++r, j += DIR)
+      march_row<R, N, ORD, COMP, MODE, DIR, false>(A, P, s, dst, hp, j, i, ic, im, ip, active, ident,
+                                                   tot, bad);
+  }
   if (nmain < nrow)
     march_row<R, N, ORD, COMP, MODE, DIR, true>(A, P, s, dst, hp, jl, i, ic, im, ip, active, ident,
                                                 tot, bad);
@@ -328,14 +388,14 @@ __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& 
 // Segments alternate direction (group parity), so two neighbouring segments
 // touch their shared halo rows at the same time -- both at their start or
 // both at their end -- and the second read hits in L2.
-template <typename R, int N, int ORD, bool COMP, int MODE>
+template <typename R, int N, int ORD, bool COMP, int MODE, bool PF>
 __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>& P, int i,
                                            bool active, int j0, int j1, int group, double (&tot)[4],
                                            int& bad) {
   if (group & 1)
-    march_dir<R, N, ORD, COMP, MODE, -1>(A, P, i, active, j0, j1, tot, bad);
+    march_dir<R, N, ORD, COMP, MODE, -1, PF>(A, P, i, active, j0, j1, tot, bad);
   else
-    march_dir<R, N, ORD, COMP, MODE, +1>(A, P, i, active, j0, j1, tot, bad);
+    march_dir<R, N, ORD, COMP, MODE, +1, PF>(A, P, i, active, j0, j1, tot, bad);
 }
 
 template <int MODE>
@@ -361,7 +421,7 @@ __device__ __forceinline__ void block_totals(const double (&tot)[4], int bad, do
   }
 }
 
-template <typename R, int N, int ORD, bool COMP, int MODE>
+template <typename R, int N, int ORD, bool COMP, int MODE, bool PF>
 __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -380,7 +440,7 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
     const int j0 = seg * A.rows;
     const int j1 = min(j0 + A.rows, A.inst.ny);
     if (j0 < A.inst.ny)
-      march_lane<R, N, ORD, COMP, MODE>(A, A.inst, i, i < A.inst.nx, j0, j1, group, tot, bad);
+      march_lane<R, N, ORD, COMP, MODE, PF>(A, A.inst, i, i < A.inst.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
     if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
@@ -519,7 +579,7 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
     const int j0 = seg * rows;
     const int j1 = min(j0 + rows, P.ny);
     const int group = it.seg0 / (64 / W);
-    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
+    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE, true>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
     if (bad) A.flag[0] = 1;
@@ -700,9 +760,14 @@ static hipError_t march_mode(int mode, const MarchArgs<R>& A, int nblocks, hipSt
     return hipGetLastError();
   }
   switch (mode) {
-    case MODE_STEP: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
-    case MODE_CHECK: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
-    default: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_AUX>), g, b, 0, st, A); break;
+    case MODE_STEP:
+      if (A.prefetch)
+        hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_STEP, true>), g, b, 0, st, A);
+      else
+        hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_STEP, false>), g, b, 0, st, A);
+      break;
+    case MODE_CHECK: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_CHECK, false>), g, b, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_march<R, N, ORD, COMP, MODE_AUX, false>), g, b, 0, st, A); break;
   }
   return hipGetLastError();
 }
