@@ -72,6 +72,72 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
     }
 
 
+def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100):
+    """Batched steady solves of the thermal-Couette sampler (seed 2026) in one
+    persistent, graph-captured run, against plain single-instance solves.
+
+    The plain leg solves a stratified sample (plain_per_size instances of
+    every N_y) one after another with the single-instance path; every
+    instance of the batch takes exactly as many steps plain as batched (the
+    arithmetic is identical, tested bitwise), so the plain wall time of the
+    whole batch is the sum over instances of steps x the measured plain time
+    per step of its size (residual checks included)."""
+    import numpy as np
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.autotune import autotune_batch
+    from paper_1004_5059_amd.tvlbm import BatchSolver, Solver
+
+    insts = inputs.couette_instances(n_inst, seed=2026)
+    shapes = autotune_batch(insts)
+    b = BatchSolver(insts, dtype="f32")
+    for c, (w, r) in shapes.items():
+        b.set_shape(c, w, r)
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
+    b.run(2 * k, tol=0.0, k_interval=k)  # warm-up, graph capture
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok, steps, r = b.run(5_000_000, tol, k)
+    t_batch = time.perf_counter() - t0
+    b.close()
+    cells = np.array([d["nx"] * d["ny"] for d in insts])
+    # plain: per-size time per step from a stratified sample
+    rng = np.random.default_rng(0)
+    per_step = {}
+    sample = []
+    for ny in sorted(set(d["ny"] for d in insts)):
+        idx = [i for i, d in enumerate(insts) if d["ny"] == ny]
+        pick = rng.choice(idx, min(plain_per_size, len(idx)), replace=False)
+        ts, ns = 0.0, 0
+        for i in pick:
+            d = insts[i]
+            s = Solver(d["nx"], d["ny"], n_gh=4, dtype="f32", tau=d["tau"], walls=True,
+                       wall_lo=(0.0, d["T_bot"]), wall_hi=(d["u_top"], d["T_top"]))
+            s.set_fields(*inputs.uniform_fields(d["nx"], d["ny"]))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            conv, n, rr = s.solve(5_000_000, tol, k)
+            ts += time.perf_counter() - t1
+            ns += n
+            sample.append(int(i))
+            s.close()
+        per_step[ny] = ts / max(ns, 1)
+    t_plain = float(sum(steps[i] * per_step[d["ny"]] for i, d in enumerate(insts)))
+    return {
+        "instances": n_inst, "converged": bool(ok), "tol": tol, "k_interval": k,
+        "batched_wall_s": round(t_batch, 3), "batched_solves_per_s": round(n_inst / t_batch, 3),
+        "plain_wall_s_est": round(t_plain, 3), "plain_solves_per_s": round(n_inst / t_plain, 3),
+        "speedup": round(t_plain / t_batch, 2),
+        "aggregate_mlups": round(float(np.sum(cells * steps)) / t_batch / 1e6, 1),
+        "steps_max": int(np.max(steps)), "steps_mean": float(np.mean(steps)),
+        "plain_sample": f"{len(sample)} instances ({plain_per_size} per N_y) solved one by one; "
+                        "whole-batch plain time = sum of steps x per-size time per step",
+        "shapes": {str(c): list(v) for c, v in shapes.items()},
+    }
+
+
 def copy_ceiling(mib: int = 1024, reps: int = 10):
     """Device-to-device copy of a buffer larger than the MALL: the achievable
     HBM bandwidth ceiling (bytes read + bytes written per second)."""
@@ -107,7 +173,7 @@ def cpu_baseline(size: int, target_s: float = 12.0):
     t = time.perf_counter()
     f = g.run(f, 1)
     one = time.perf_counter() - t
-    steps = max(1, min(50, int(target_s / max(one, 1e-3))))
+    steps = max(1, min(2000, int(target_s / max(one, 1e-3))))
     t = time.perf_counter()
     g.run(f, steps)
     dt = time.perf_counter() - t
@@ -139,17 +205,27 @@ def main():
     ap.add_argument("--no-d2q36", action="store_true")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 run")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the TVLBM path here is single-GPU "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
-    r16 = run_lattice(4, args.size, args.steps, args.warmup, args.variant)
-    r36 = None if args.no_d2q36 else run_lattice(6, args.size, args.steps, args.warmup, args.variant)
-    big = None if args.no_4096 else run_lattice(4, 4096, max(20, args.steps // 10), 5, args.variant)
-    cp = None if args.no_copy else copy_ceiling()
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.size)
+    def leg(name, fn, *a):
+        t0 = time.perf_counter()
+        r = fn(*a)
+        print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        return r
+
+    r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, args.variant)
+    r36 = None if args.no_d2q36 else leg("D2Q36", run_lattice, 6, args.size, args.steps,
+                                         args.warmup, args.variant)
+    big = None if args.no_4096 else leg("D2Q16 4096", run_lattice, 4, 4096,
+                                        max(20, args.steps // 10), 5, args.variant)
+    cp = None if args.no_copy else leg("copy ceiling", copy_ceiling)
+    bat = None if args.no_batched else leg("batched", run_batched)
+    cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
     achieved = r16["achieved_gbs"]
     out = {
         "metric": METRIC,
@@ -181,6 +257,7 @@ def main():
             "mlups": round(big["mlups"], 1), "achieved_gbs": round(big["achieved_gbs"], 1),
             "frac": round(big["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": big["variant"]},
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
+        "batched": bat,
     }
     print(json.dumps(out), flush=True)
 

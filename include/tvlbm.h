@@ -78,7 +78,8 @@ typedef struct tvlbm_desc {
   double wall_lo_ux, wall_lo_T; /* wall at y = 0: x velocity, temperature         */
   double wall_hi_ux, wall_hi_T; /* wall at y = H                                  */
   const double *dy;    /* host, ny row heights in cells (x spacing is 1);         */
-                       /* NULL = unit rows.  Non-uniform rows need walls.          */
+                       /* NULL = unit rows.  EUNSUPPORTED if a row would need     */
+                       /* more than four source rows (Sec. III meshes)            */
   void *f_a, *f_b;     /* device, each q*ny*ld elements of dtype, caller-owned    */
   void *stream;        /* hipStream_t, or NULL for the default stream             */
 } tvlbm_desc;
@@ -197,6 +198,21 @@ int tvlbm_batch_fields(tvlbm_batch *b, void *fields_out);
  * depend on the shape. */
 int tvlbm_batch_set_shape(tvlbm_batch *b, int32_t max_nx, int32_t width,
                           int32_t rows);
+
+/* Launch tuning of a batched run; results do not depend on it. */
+typedef struct tvlbm_batch_tuning {
+  int32_t prefetch;    /* 1: step kernel with software-pipelined row loads;  */
+                       /* 0: without (fewer registers, more waves resident)  */
+  int32_t tail_active; /* > 0: once at most this many instances are still    */
+                       /* unconverged, every remaining instance is cut into   */
+                       /* items of the tail shape below; 0: never             */
+  int32_t tail_width;  /* 16, 32 or 64 columns                               */
+  int32_t tail_rows;   /* rows per lane segment, 1..255                      */
+} tvlbm_batch_tuning;
+/* Defaults: prefetch 1, tail_active 0, tail shape 64 x 1.  EINVAL on values
+ * outside the ranges above.  Synchronises the batch's stream. */
+int tvlbm_batch_set_tuning(tvlbm_batch *b, const tvlbm_batch_tuning *t);
+int tvlbm_batch_get_tuning(const tvlbm_batch *b, tvlbm_batch_tuning *t);
 
 #ifdef __cplusplus
 }

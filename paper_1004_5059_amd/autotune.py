@@ -62,3 +62,50 @@ def autotune(solver, steps: int = 20, reps: int = 2, cache_path: str | None = No
         with open(cache_path, "w") as fh:
             json.dump(data, fh, indent=1)
     return v, times
+
+
+BATCH_SHAPES = [(16, 8), (16, 16), (32, 8), (32, 16), (64, 4), (64, 8)]
+SIZE_CLASSES = [16, 32, 64, 1 << 30]  # max nx of each class
+
+
+def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: str = "f32"):
+    """Per size class (max N_x), pick the (strip width, rows per segment)
+    of the batched kernel by coordinate descent over the classes, timing a
+    fixed number of steps of the whole batch.  Returns {max_nx: (w, rows)}."""
+    import time
+
+    import torch
+
+    from . import inputs
+    from .tvlbm import BatchSolver
+
+    b = BatchSolver(instances, dtype=dtype)
+    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in instances])
+    max_nx = max(d["nx"] for d in instances)
+    classes = [c for c in SIZE_CLASSES if c < (1 << 30)] + [1 << 30]
+    choice = {c: (16 if c <= 16 else 32 if c <= 32 else 64, 8) for c in classes}
+
+    def timed():
+        for c, (w, r) in choice.items():
+            b.set_shape(c, w, r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps, tol=0.0, k_interval=k_interval)
+        return time.perf_counter() - t0
+
+    timed()  # warm-up (graph capture)
+    for c in classes:
+        lo = 0 if c == classes[0] else classes[classes.index(c) - 1]
+        if lo >= max_nx:
+            continue
+        best, best_t = choice[c], float("inf")
+        for w, r in BATCH_SHAPES:
+            if w > max(16, c) and c < (1 << 30):
+                continue
+            choice[c] = (w, r)
+            t = timed()
+            if t < best_t:
+                best, best_t = (w, r), t
+        choice[c] = best
+    b.close()
+    return choice

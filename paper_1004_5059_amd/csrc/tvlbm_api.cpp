@@ -768,7 +768,7 @@ struct tvlbm_batch {
   Work* d_all = nullptr;
   Work* d_work = nullptr;
   int32_t* d_item_start = nullptr;
-  int32_t* d_dst_off = nullptr;
+  double* d_rpart = nullptr;  // residual partials, n_inst * RESID_SLICES * 2
   int32_t* d_nwork = nullptr;
   int32_t* d_ntotal = nullptr;
   int32_t* d_remaining = nullptr;
@@ -784,6 +784,17 @@ struct tvlbm_batch {
   std::vector<Shape> shapes;
   int n_items = 0;
   int items_cap = 0;
+  // Tail phase: once at most tail_active instances are unconverged, the
+  // work list is rebuilt from items of the single shape (tail_width,
+  // tail_rows), which cuts the few remaining grids into more, shorter
+  // segments; the arithmetic is the same.
+  Work* d_all_tail = nullptr;
+  int32_t* d_item_start_tail = nullptr;
+  int n_items_tail = 0;
+  int tail_cap = 0;
+  int prefetch = 1;
+  int tail_active = 0, tail_width = 64, tail_rows = 1;
+  hipGraphExec_t gexec_tail = nullptr;
   bool initialised = false;
   bool stepped = false;
   hipGraphExec_t gexec = nullptr;
@@ -840,13 +851,17 @@ const tvlbm_batch::Shape& shape_for(const tvlbm_batch* b, int nx) {
   return b->shapes.back();
 }
 
-int build_items(tvlbm_batch* b) {
-  std::vector<Work> all;
-  std::vector<int32_t> start(b->inst.size() + 1, 0);
+// Work items of every instance, each cut into strips of S.width columns and
+// segments of S.rows rows; `start` gets each instance's first item.
+template <typename ShapeOf>
+void make_items(const tvlbm_batch* b, ShapeOf shape_of, std::vector<Work>& all,
+                std::vector<int32_t>& start) {
+  all.clear();
+  start.assign(b->inst.size() + 1, 0);
   for (size_t k = 0; k < b->inst.size(); ++k) {
     start[k] = (int32_t)all.size();
     const tvlbm_inst& I = b->inst[k];
-    const auto& S = shape_for(b, I.nx);
+    const tvlbm_batch::Shape S = shape_of(I.nx);
     const int spw = 64 / S.width;
     const int nseg = (I.ny + S.rows - 1) / S.rows;
     for (int x0 = 0; x0 < I.nx; x0 += S.width)
@@ -854,32 +869,62 @@ int build_items(tvlbm_batch* b) {
         all.push_back(Work{(int32_t)k, x0, sg, S.width | (S.rows << 8)});
   }
   start[b->inst.size()] = (int32_t)all.size();
+}
+
+void drop_graphs(tvlbm_batch* b) {
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->gexec_tail) hipGraphExecDestroy(b->gexec_tail);
+  b->gexec = b->gexec_tail = nullptr;
+}
+
+int build_items(tvlbm_batch* b) {
+  std::vector<Work> all, tail;
+  std::vector<int32_t> start, tail_start;
+  make_items(b, [b](int nx) { return shape_for(b, nx); }, all, start);
   b->n_items = (int)all.size();
+  b->n_items_tail = 0;
+  if (b->tail_active > 0) {
+    const tvlbm_batch::Shape T{0, b->tail_width, b->tail_rows};
+    make_items(b, [T](int) { return T; }, tail, tail_start);
+    b->n_items_tail = (int)tail.size();
+  }
   if (b->n_items > b->items_cap) {
     hipFree(b->d_all);
-    hipFree(b->d_work);
-    b->d_all = b->d_work = nullptr;
-    BHIP(b, hipMalloc(&b->d_all, sizeof(Work) * all.size()));
-    BHIP(b, hipMalloc(&b->d_work, sizeof(Work) * all.size()));
+    b->d_all = nullptr;
+    BHIP(b, hipMalloc(&b->d_all, sizeof(Work) * b->n_items));
     b->items_cap = b->n_items;
   }
+  if (b->n_items_tail > b->tail_cap) {
+    hipFree(b->d_all_tail);
+    b->d_all_tail = nullptr;
+    BHIP(b, hipMalloc(&b->d_all_tail, sizeof(Work) * b->n_items_tail));
+    b->tail_cap = b->n_items_tail;
+  }
+  // the live work list holds items of either list
+  hipFree(b->d_work);
+  b->d_work = nullptr;
+  BHIP(b, hipMalloc(&b->d_work, sizeof(Work) * std::max(b->n_items, b->n_items_tail)));
   BHIP(b, hipMemcpy(b->d_all, all.data(), sizeof(Work) * all.size(), hipMemcpyHostToDevice));
   BHIP(b, hipMemcpy(b->d_item_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice));
-  BHIP(b, hipMemcpy(b->d_ntotal, &b->n_items, sizeof(int32_t), hipMemcpyHostToDevice));
-  if (b->gexec) {
-    hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
+  if (b->n_items_tail > 0) {
+    BHIP(b, hipMemcpy(b->d_all_tail, tail.data(), sizeof(Work) * tail.size(), hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_item_start_tail, tail_start.data(), sizeof(int32_t) * tail_start.size(),
+                      hipMemcpyHostToDevice));
   }
+  BHIP(b, hipMemcpy(b->d_ntotal, &b->n_items, sizeof(int32_t), hipMemcpyHostToDevice));
+  drop_graphs(b);
   return TVLBM_OK;
 }
 
-int batch_blocks(const tvlbm_batch* b) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->n_items, 4), 2048));
+// Persistent grid of the batched step: one wavefront per item up to 2048
+// workgroups, rounded to a multiple of 8 for the XCD-contiguous item order.
+int batch_blocks(int n_items) {
+  return (int)std::min<int64_t>(ceil_div(std::max<int64_t>(ceil_div(n_items, 4), 1), 8) * 8, 2048);
 }
 
 template <typename R>
 int batch_march(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
-                const Work* work) {
+                const Work* work, int nblocks) {
   MarchArgs<R> A;
   std::memset(&A, 0, sizeof A);
   A.lat = std::is_same<R, float>::value ? *(Lat<R>*)(void*)&b->latf : *(Lat<R>*)(void*)&b->latd;
@@ -891,14 +936,23 @@ int batch_march(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, c
   A.dst = (R*)dst;
   A.fields = (R*)b->d_fields;
   A.flag = b->d_flag;
-  BHIP(b, launch_march_batch(b->hl.n, b->comp, mode, A, batch_blocks(b), b->st));
+  BHIP(b, launch_march_batch(b->hl.n, b->comp, mode, b->prefetch != 0, A, nblocks, b->st));
   return TVLBM_OK;
 }
 
 int bmarch(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
-           const Work* work) {
-  return b->f64 ? batch_march<double>(b, mode, aux, src, dst, nwork, work)
-                : batch_march<float>(b, mode, aux, src, dst, nwork, work);
+           const Work* work, int nblocks) {
+  return b->f64 ? batch_march<double>(b, mode, aux, src, dst, nwork, work, nblocks)
+                : batch_march<float>(b, mode, aux, src, dst, nwork, work, nblocks);
+}
+
+// Rebuild the live work list from the active instances' items of the bulk
+// or the tail list.
+int compact(tvlbm_batch* b, bool tail) {
+  BHIP(b, launch_batch_compact(b->d_active, tail ? b->d_item_start_tail : b->d_item_start,
+                               tail ? b->d_all_tail : b->d_all, b->d_work, b->d_nwork,
+                               b->d_remaining, (int)b->inst.size(), b->st));
+  return TVLBM_OK;
 }
 
 template <typename R>
@@ -913,6 +967,7 @@ int batch_resid(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
   C.steps = b->d_steps;
   C.resid = b->d_resid;
   C.flag = b->d_flag;
+  C.part = b->d_rpart;
   C.K = K;
   C.tol = tol;
   C.max_steps = max_steps;
@@ -923,16 +978,31 @@ int batch_resid(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
 // One chunk: K steps (the last one also writes the fields), the residual
 // and the compaction of the work list.  At chunk boundaries every instance's
 // post-collision state is in buf[0] (K is even).
-int enqueue_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
+int enqueue_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps, bool tail) {
+  const int nblocks = batch_blocks(tail ? b->n_items_tail : b->n_items);
   for (int s = 0; s < K; ++s) {
     const int mode = (s == K - 1) ? MODE_CHECK : MODE_STEP;
-    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work);
+    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work, nblocks);
     if (rc) return rc;
   }
   int rc = b->f64 ? batch_resid<double>(b, K, tol, max_steps) : batch_resid<float>(b, K, tol, max_steps);
   if (rc) return rc;
-  BHIP(b, launch_batch_compact(b->d_active, b->d_item_start, b->d_all, b->d_work, b->d_dst_off,
-                               b->d_nwork, b->d_remaining, (int)b->inst.size(), b->st));
+  return compact(b, tail);
+}
+
+// The chunk captured as a graph on the batch's stream.
+int capture_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps, bool tail,
+                  hipGraphExec_t* out) {
+  BHIP(b, hipStreamSynchronize(b->st));
+  BHIP(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_chunk(b, K, tol, max_steps, tail);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->st, &g);
+  if (rc) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return bfail(b, TVLBM_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) { *out = nullptr; return bfail(b, TVLBM_EHIP, "graph instantiate"); }
   return TVLBM_OK;
 }
 
@@ -955,9 +1025,10 @@ int tvlbm_batch_sizes(const tvlbm_batch_desc* d, int64_t* pop_elems, int64_t* fi
 int tvlbm_batch_destroy(tvlbm_batch* b) {
   if (!b) return TVLBM_EINVAL;
   if (b->st) hipStreamSynchronize(b->st);
-  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  drop_graphs(b);
   hipFree(b->d_insts); hipFree(b->d_all); hipFree(b->d_work); hipFree(b->d_item_start);
-  hipFree(b->d_dst_off); hipFree(b->d_nwork); hipFree(b->d_ntotal); hipFree(b->d_remaining);
+  hipFree(b->d_all_tail); hipFree(b->d_item_start_tail);
+  hipFree(b->d_rpart); hipFree(b->d_nwork); hipFree(b->d_ntotal); hipFree(b->d_remaining);
   hipFree(b->d_active); hipFree(b->d_have_prev); hipFree(b->d_steps); hipFree(b->d_resid);
   hipFree(b->d_flag); hipFree(b->d_fields); hipFree(b->d_prev);
   if (b->h_remaining) hipHostFree(b->h_remaining);
@@ -1006,7 +1077,8 @@ int tvlbm_batch_init(const tvlbm_batch_desc* d, tvlbm_batch** out) {
   const size_t esz = b->f64 ? 8 : 4;
   bool ok = hipMalloc(&b->d_insts, isz * n) == hipSuccess &&
             hipMalloc(&b->d_item_start, sizeof(int32_t) * (n + 1)) == hipSuccess &&
-            hipMalloc(&b->d_dst_off, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc(&b->d_item_start_tail, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            hipMalloc(&b->d_rpart, sizeof(double) * 2 * RESID_SLICES * n) == hipSuccess &&
             hipMalloc(&b->d_nwork, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_ntotal, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_remaining, sizeof(int32_t)) == hipSuccess &&
@@ -1045,6 +1117,28 @@ int tvlbm_batch_set_shape(tvlbm_batch* b, int32_t max_nx, int32_t width, int32_t
             [](const tvlbm_batch::Shape& x, const tvlbm_batch::Shape& y) { return x.max_nx < y.max_nx; });
   BHIP(b, hipStreamSynchronize(b->st));
   return build_items(b);
+}
+
+int tvlbm_batch_set_tuning(tvlbm_batch* b, const tvlbm_batch_tuning* t) {
+  if (!b || !t || (t->prefetch != 0 && t->prefetch != 1) || t->tail_active < 0 ||
+      !(t->tail_width == 16 || t->tail_width == 32 || t->tail_width == 64) || t->tail_rows < 1 ||
+      t->tail_rows > 255)
+    return bfail(b, TVLBM_EINVAL, "tuning");
+  BHIP(b, hipStreamSynchronize(b->st));
+  b->prefetch = t->prefetch;
+  b->tail_active = t->tail_active;
+  b->tail_width = t->tail_width;
+  b->tail_rows = t->tail_rows;
+  return build_items(b);
+}
+
+int tvlbm_batch_get_tuning(const tvlbm_batch* b, tvlbm_batch_tuning* t) {
+  if (!b || !t) return TVLBM_EINVAL;
+  t->prefetch = b->prefetch;
+  t->tail_active = b->tail_active;
+  t->tail_width = b->tail_width;
+  t->tail_rows = b->tail_rows;
+  return TVLBM_OK;
 }
 
 int tvlbm_batch_set_fields(tvlbm_batch* b, const void* fields) {
@@ -1094,36 +1188,37 @@ int tvlbm_batch_run(tvlbm_batch* b, int64_t max_steps, double tol, int32_t K, in
   // residual (as the single-instance solve does)
   {
     const int aux = AUX_FIELDS | (b->stepped ? 0 : AUX_IDENTITY);
-    int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all);
+    int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all, batch_blocks(b->n_items));
     if (rc) return rc;
     const size_t esz = b->f64 ? 8 : 4;
     BHIP(b, hipMemcpyAsync(b->d_prev, b->d_fields, esz * b->field_elems, hipMemcpyDeviceToDevice, b->st));
   }
   BHIP(b, hipMemcpyAsync(b->d_have_prev, ones.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->st));
   BHIP(b, hipMemcpyAsync(b->d_steps, zeros64.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, b->st));
-  BHIP(b, launch_batch_compact(b->d_active, b->d_item_start, b->d_all, b->d_work, b->d_dst_off,
-                               b->d_nwork, b->d_remaining, n, b->st));
-  if (!b->gexec || b->g_K != K || b->g_tol != tol || b->g_max != max_steps) {
-    if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
-    BHIP(b, hipStreamSynchronize(b->st));
-    BHIP(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_chunk(b, K, tol, max_steps);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(b->st, &g);
-    if (rc) { if (g) hipGraphDestroy(g); return rc; }
-    if (e != hipSuccess) return bfail(b, TVLBM_EHIP, std::string("capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) { b->gexec = nullptr; return bfail(b, TVLBM_EHIP, "graph instantiate"); }
-    b->g_K = K; b->g_tol = tol; b->g_max = max_steps;
-  }
+  if (b->g_K != K || b->g_tol != tol || b->g_max != max_steps) drop_graphs(b);
+  b->g_K = K; b->g_tol = tol; b->g_max = max_steps;
+  auto want_tail = [b](int remaining) { return b->tail_active > 0 && remaining <= b->tail_active; };
+  bool tail = want_tail(n);
+  int rc = compact(b, tail);
+  if (rc) return rc;
   const int64_t max_chunks = (max_steps + K - 1) / K + 1;
   for (int64_t c = 0; c < max_chunks; ++c) {
-    BHIP(b, hipGraphLaunch(b->gexec, b->st));
+    hipGraphExec_t& ge = tail ? b->gexec_tail : b->gexec;
+    if (!ge) {
+      rc = capture_chunk(b, K, tol, max_steps, tail, &ge);
+      if (rc) return rc;
+    }
+    BHIP(b, hipGraphLaunch(ge, b->st));
     BHIP(b, hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int32_t), hipMemcpyDeviceToHost, b->st));
     BHIP(b, hipStreamSynchronize(b->st));
     b->stepped = true;
-    if (*b->h_remaining == 0) break;
+    const int remaining = *b->h_remaining;
+    if (remaining == 0) break;
+    if (!tail && want_tail(remaining)) {
+      tail = true;
+      rc = compact(b, true);
+      if (rc) return rc;
+    }
   }
   std::vector<double> r(n);
   int32_t flag = 0;
@@ -1142,7 +1237,7 @@ int tvlbm_batch_fields(tvlbm_batch* b, void* out) {
   if (!b || !out) return bfail(b, TVLBM_EINVAL, "null");
   if (!b->initialised) return bfail(b, TVLBM_EINVAL, "fields not set");
   const int aux = AUX_FIELDS | (b->stepped ? 0 : AUX_IDENTITY);
-  int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all);
+  int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all, batch_blocks(b->n_items));
   if (rc) return rc;
   const size_t esz = b->f64 ? 8 : 4;
   BHIP(b, hipMemcpyAsync(out, b->d_fields, esz * b->field_elems, hipMemcpyDeviceToDevice, b->st));

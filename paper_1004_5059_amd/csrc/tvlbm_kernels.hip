@@ -563,14 +563,26 @@ __global__ __launch_bounds__(256) void k_rows(const MarchArgs<R> A) {
 // wavefront takes work items (instance, strip, segment group) until the
 // list, whose live length is read from device memory, is exhausted.  The
 // per-instance parameters are read from device memory with scalar loads.
-template <typename R, int N, int ORD, bool COMP, int MODE>
+template <typename R, int N, int ORD, bool COMP, int MODE, bool PF>
 __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_work = *A.n_work;
   double tot[4] = {0.0, 0.0, 0.0, 0.0};
   int bad = 0;
-  for (int w = blockIdx.x * 4 + wave; w < n_work; w += gridDim.x * 4) {
+  // Workgroups go round-robin to the 8 XCDs.  Split the live list into 8
+  // equal contiguous ranges, one per XCD, so that adjacent segments of a
+  // strip, which share halo rows, run on one XCD and hit its L2; within a
+  // range the XCD's workgroups stride over the items.
+  int lo = 0, hi = n_work, first = blockIdx.x * 4 + wave, stride = gridDim.x * 4;
+  if ((gridDim.x & 7) == 0) {
+    const int x = blockIdx.x & 7;
+    lo = (int)((int64_t)n_work * x / 8);
+    hi = (int)((int64_t)n_work * (x + 1) / 8);
+    first = lo + (int)(blockIdx.x >> 3) * 4 + wave;
+    stride = (int)(gridDim.x >> 3) * 4;
+  }
+  for (int w = first; w < hi; w += stride) {
     const Work it = A.work[w];
     const Inst<R>& P = A.insts[it.inst];
     const int W = it.shape & 0xff, rows = it.shape >> 8;
@@ -579,28 +591,30 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
     const int j0 = seg * rows;
     const int j1 = min(j0 + rows, P.ny);
     const int group = it.seg0 / (64 / W);
-    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE, true>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
+    if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE, PF>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
     if (bad) A.flag[0] = 1;
   }
 }
 
-// Per-instance residual after a chunk of K steps (one workgroup per
-// instance): r = ||q - q_prev|| / (K ||q||) over the instance's stacked
-// fields; the snapshot is updated, the step count advanced, and the instance
-// retired when r < tol or its step budget is spent.
+// Per-instance residual after a chunk of K steps,
+// r = ||q - q_prev|| / (K ||q||) over the instance's stacked fields, in two
+// fixed-order passes.  Pass 1: RESID_SLICES workgroups per active instance
+// each reduce one contiguous slice of its fields into a partial pair and
+// refresh that slice of the snapshot.
 template <typename R>
-__global__ __launch_bounds__(256) void k_batch_resid(const BatchCtl<R> C) {
+__global__ __launch_bounds__(256) void k_batch_resid_part(const BatchCtl<R> C) {
   __shared__ double sh[2][4];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / RESID_SLICES, sl = blockIdx.x % RESID_SLICES;
   if (!C.active[b]) return;
   const Inst<R>& P = C.insts[b];
   const int64_t n = (int64_t)4 * P.nx * P.ny;
+  const int64_t k0 = n * sl / RESID_SLICES, k1 = n * (sl + 1) / RESID_SLICES;
   const R* q = C.fields + P.fld;
   R* qp = C.prev + P.fld;
   double a = 0.0, s = 0.0;
-  for (int64_t k = threadIdx.x; k < n; k += 256) {
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
     const double v = (double)q[k], dv = v - (double)qp[k];
     a += dv * dv;
     s += v * v;
@@ -613,47 +627,71 @@ __global__ __launch_bounds__(256) void k_batch_resid(const BatchCtl<R> C) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) { sh[0][wave] = a; sh[1][wave] = s; }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double A2 = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
-    const double S2 = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
-    const int64_t st = C.steps[b] + C.K;
-    C.steps[b] = st;
-    const double r = C.have_prev[b] ? __builtin_sqrt(A2) / ((double)C.K * __builtin_sqrt(S2))
-                                    : __builtin_inf();
-    C.have_prev[b] = 1;
-    C.resid[b] = r;
-    if (!(r == r)) C.flag[0] = 1;
-    if (!(r >= C.tol) || st >= C.max_steps) C.active[b] = 0;
+  if (threadIdx.x < 2) {
+    const int c = threadIdx.x;
+    C.part[(int64_t)blockIdx.x * 2 + c] = ((sh[c][0] + sh[c][1]) + sh[c][2]) + sh[c][3];
   }
 }
 
-// Rebuild the work list from the active instances (single workgroup).
+// Pass 2 (one thread per instance): sum the slices in order, advance the
+// step count, and retire the instance when r < tol or its step budget is
+// spent.
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_resid_fin(const BatchCtl<R> C, int n_inst) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n_inst || !C.active[b]) return;
+  double A2 = 0.0, S2 = 0.0;
+  for (int sl = 0; sl < RESID_SLICES; ++sl) {
+    A2 += C.part[((int64_t)b * RESID_SLICES + sl) * 2];
+    S2 += C.part[((int64_t)b * RESID_SLICES + sl) * 2 + 1];
+  }
+  const int64_t st = C.steps[b] + C.K;
+  C.steps[b] = st;
+  const double r = C.have_prev[b] ? __builtin_sqrt(A2) / ((double)C.K * __builtin_sqrt(S2))
+                                  : __builtin_inf();
+  C.have_prev[b] = 1;
+  C.resid[b] = r;
+  if (!(r == r)) C.flag[0] = 1;
+  if (!(r >= C.tol) || st >= C.max_steps) C.active[b] = 0;
+}
+
+// Rebuild the work list from the active instances' items, in instance
+// order; one workgroup per instance.  Each workgroup sums the item counts
+// of the active instances before it (block b = 0 also writes the totals),
+// then copies its own items.
 __global__ __launch_bounds__(256) void k_batch_compact(const int32_t* __restrict__ active,
                                                        const int32_t* __restrict__ item_start,
                                                        const Work* __restrict__ all,
                                                        Work* __restrict__ work,
-                                                       int32_t* __restrict__ dst_off,
                                                        int32_t* __restrict__ n_work,
                                                        int32_t* __restrict__ remaining,
                                                        int n_inst) {
-  if (threadIdx.x == 0) {
-    int o = 0, rem = 0;
-    for (int b = 0; b < n_inst; ++b) {
-      dst_off[b] = o;
-      if (active[b]) {
-        o += item_start[b + 1] - item_start[b];
-        ++rem;
-      }
-    }
-    *n_work = o;
-    *remaining = rem;
+  __shared__ int sh[3][4];
+  const int b = blockIdx.x;
+  const int lim = b == 0 ? n_inst : b;
+  int before = 0, total = 0, rem = 0;
+  for (int k = threadIdx.x; k < lim; k += 256) {
+    const int cnt = active[k] ? item_start[k + 1] - item_start[k] : 0;
+    if (k < b) before += cnt;
+    total += cnt;
+    rem += active[k] ? 1 : 0;
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    before += __shfl_xor(before, off, 64);
+    total += __shfl_xor(total, off, 64);
+    rem += __shfl_xor(rem, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sh[0][wave] = before; sh[1][wave] = total; sh[2][wave] = rem; }
   __syncthreads();
-  for (int b = 0; b < n_inst; ++b) {
-    if (!active[b]) continue;
-    const int s0 = item_start[b], cnt = item_start[b + 1] - s0, o = dst_off[b];
-    for (int t = threadIdx.x; t < cnt; t += 256) work[o + t] = all[s0 + t];
+  const int o = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+  if (b == 0 && threadIdx.x == 0) {
+    *n_work = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    *remaining = sh[2][0] + sh[2][1] + sh[2][2] + sh[2][3];
   }
+  if (!active[b]) return;
+  const int s0 = item_start[b], cnt = item_start[b + 1] - s0;
+  for (int t = threadIdx.x; t < cnt; t += 256) work[o + t] = all[s0 + t];
 }
 
 // ----------------------------------------------------------------- init ---
@@ -814,52 +852,60 @@ hipError_t launch_init(int n, bool comp, const InitArgs<double>& A, hipStream_t 
   return init_lat<double, false>(n, A, st);
 }
 
-template <typename R, int N, int ORD, bool COMP>
+template <typename R, int N, int ORD, bool COMP, bool PF>
 static hipError_t batch_mode(int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
   dim3 g(nblocks), b(256);
   switch (mode) {
-    case MODE_STEP: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_STEP>), g, b, 0, st, A); break;
-    case MODE_CHECK: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_CHECK>), g, b, 0, st, A); break;
-    default: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_AUX>), g, b, 0, st, A); break;
+    case MODE_STEP: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_STEP, PF>), g, b, 0, st, A); break;
+    case MODE_CHECK: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_CHECK, PF>), g, b, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_march_batch<R, N, ORD, COMP, MODE_AUX, false>), g, b, 0, st, A); break;
   }
   return hipGetLastError();
 }
 
 template <typename R, bool COMP>
-static hipError_t batch_lat(int n, int mode, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+static hipError_t batch_lat(int n, int mode, bool pf, const MarchArgs<R>& A, int nblocks,
+                            hipStream_t st) {
   switch (n) {
-    case 3: return batch_mode<R, 3, 2, COMP>(mode, A, nblocks, st);
-    case 4: return batch_mode<R, 4, 3, COMP>(mode, A, nblocks, st);
-    case 6: return batch_mode<R, 6, 4, COMP>(mode, A, nblocks, st);
+    case 3: return pf ? batch_mode<R, 3, 2, COMP, true>(mode, A, nblocks, st)
+                      : batch_mode<R, 3, 2, COMP, false>(mode, A, nblocks, st);
+    case 4: return pf ? batch_mode<R, 4, 3, COMP, true>(mode, A, nblocks, st)
+                      : batch_mode<R, 4, 3, COMP, false>(mode, A, nblocks, st);
+    case 6: return pf ? batch_mode<R, 6, 4, COMP, true>(mode, A, nblocks, st)
+                      : batch_mode<R, 6, 4, COMP, false>(mode, A, nblocks, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
-                              hipStream_t st) {
-  return comp ? batch_lat<float, true>(n, mode, A, nblocks, st)
-              : batch_lat<float, false>(n, mode, A, nblocks, st);
+hipError_t launch_march_batch(int n, bool comp, int mode, bool prefetch, const MarchArgs<float>& A,
+                              int nblocks, hipStream_t st) {
+  return comp ? batch_lat<float, true>(n, mode, prefetch, A, nblocks, st)
+              : batch_lat<float, false>(n, mode, prefetch, A, nblocks, st);
 }
-hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
-                              hipStream_t st) {
+hipError_t launch_march_batch(int n, bool comp, int mode, bool prefetch, const MarchArgs<double>& A,
+                              int nblocks, hipStream_t st) {
   (void)comp;
-  return batch_lat<double, false>(n, mode, A, nblocks, st);
+  return batch_lat<double, false>(n, mode, prefetch, A, nblocks, st);
 }
 
-hipError_t launch_batch_resid(const BatchCtl<float>& C, int n_inst, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_resid<float>, dim3(n_inst), dim3(256), 0, st, C);
+template <typename R>
+static hipError_t batch_resid_impl(const BatchCtl<R>& C, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_resid_part<R>, dim3(n_inst * RESID_SLICES), dim3(256), 0, st, C);
+  hipLaunchKernelGGL(k_batch_resid_fin<R>, dim3((n_inst + 255) / 256), dim3(256), 0, st, C, n_inst);
   return hipGetLastError();
 }
+hipError_t launch_batch_resid(const BatchCtl<float>& C, int n_inst, hipStream_t st) {
+  return batch_resid_impl(C, n_inst, st);
+}
 hipError_t launch_batch_resid(const BatchCtl<double>& C, int n_inst, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_resid<double>, dim3(n_inst), dim3(256), 0, st, C);
-  return hipGetLastError();
+  return batch_resid_impl(C, n_inst, st);
 }
 
 hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start, const Work* all,
-                                Work* work, int32_t* dst_off, int32_t* n_work, int32_t* remaining,
-                                int n_inst, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(256), 0, st, active, item_start, all, work,
-                     dst_off, n_work, remaining, n_inst);
+                                Work* work, int32_t* n_work, int32_t* remaining, int n_inst,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_compact, dim3(n_inst), dim3(256), 0, st, active, item_start, all, work,
+                     n_work, remaining, n_inst);
   return hipGetLastError();
 }
 

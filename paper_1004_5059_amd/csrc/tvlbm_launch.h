@@ -30,20 +30,24 @@ struct BatchCtl {
   int64_t* steps;
   double* resid;
   int32_t* flag;
+  double* part;        // [n_inst][RESID_SLICES][2] partial sums
   int32_t K;
   double tol;
   int64_t max_steps;
 };
+// Workgroups per instance in the batched residual's first pass.
+constexpr int RESID_SLICES = 16;
 
-hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
-                              hipStream_t st);
-hipError_t launch_march_batch(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
-                              hipStream_t st);
+// prefetch selects the software-pipelined row loads for the step modes.
+hipError_t launch_march_batch(int n, bool comp, int mode, bool prefetch, const MarchArgs<float>& A,
+                              int nblocks, hipStream_t st);
+hipError_t launch_march_batch(int n, bool comp, int mode, bool prefetch, const MarchArgs<double>& A,
+                              int nblocks, hipStream_t st);
 hipError_t launch_batch_resid(const BatchCtl<float>& C, int n_inst, hipStream_t st);
 hipError_t launch_batch_resid(const BatchCtl<double>& C, int n_inst, hipStream_t st);
 hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start, const Work* all,
-                                Work* work, int32_t* dst_off, int32_t* n_work, int32_t* remaining,
-                                int n_inst, hipStream_t st);
+                                Work* work, int32_t* n_work, int32_t* remaining, int n_inst,
+                                hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
                         hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,

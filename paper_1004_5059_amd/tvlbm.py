@@ -88,6 +88,11 @@ class tvlbm_batch_desc(ctypes.Structure):
     ]
 
 
+class tvlbm_batch_tuning(ctypes.Structure):
+    _fields_ = [("prefetch", ctypes.c_int32), ("tail_active", ctypes.c_int32),
+                ("tail_width", ctypes.c_int32), ("tail_rows", ctypes.c_int32)]
+
+
 class TvlbmError(RuntimeError):
     def __init__(self, code: int, detail: str = ""):
         self.code = code
@@ -135,6 +140,8 @@ def lib():
         "tvlbm_batch_run": [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _i64p, _dp],
         "tvlbm_batch_fields": [_vp, _vp],
         "tvlbm_batch_set_shape": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+        "tvlbm_batch_set_tuning": [_vp, ctypes.c_void_p],
+        "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -404,6 +411,18 @@ def tvlbm_batch_set_shape(h, max_nx: int, width: int, rows: int):
     _check(lib().tvlbm_batch_set_shape(h, int(max_nx), int(width), int(rows)))
 
 
+def tvlbm_batch_set_tuning(h, prefetch: int, tail_active: int, tail_width: int, tail_rows: int):
+    t = tvlbm_batch_tuning(int(prefetch), int(tail_active), int(tail_width), int(tail_rows))
+    _check(lib().tvlbm_batch_set_tuning(h, ctypes.byref(t)))
+
+
+def tvlbm_batch_get_tuning(h):
+    t = tvlbm_batch_tuning()
+    _check(lib().tvlbm_batch_get_tuning(h, ctypes.byref(t)))
+    return {"prefetch": t.prefetch, "tail_active": t.tail_active, "tail_width": t.tail_width,
+            "tail_rows": t.tail_rows}
+
+
 class BatchSolver:
     """Many walled channels (periodic in x) solved together on one GPU.
 
@@ -486,6 +505,13 @@ class BatchSolver:
 
     def set_shape(self, max_nx: int, width: int, rows: int):
         tvlbm_batch_set_shape(self.h, max_nx, width, rows)
+
+    def set_tuning(self, prefetch: int = 1, tail_active: int = 0, tail_width: int = 64,
+                   tail_rows: int = 1):
+        tvlbm_batch_set_tuning(self.h, prefetch, tail_active, tail_width, tail_rows)
+
+    def tuning(self):
+        return tvlbm_batch_get_tuning(self.h)
 
     def run(self, max_steps: int, tol: float = 1e-8, k_interval: int = 100):
         return tvlbm_batch_run(self.h, self.n, max_steps, tol, k_interval)

@@ -91,3 +91,38 @@ def test_batch_retires_converged_instances_like_single_solves():
         s.close()
     assert steps[0] != steps[1]
     b.close()
+
+
+@pytest.mark.parametrize("tuning", [dict(prefetch=0), dict(prefetch=1, tail_active=1, tail_rows=1),
+                                    dict(prefetch=0, tail_active=2, tail_width=32, tail_rows=2),
+                                    dict(prefetch=0, tail_active=3, tail_width=16, tail_rows=5)])
+def test_batch_tuning_does_not_change_results(tuning):
+    """Prefetch on/off and the switch to the tail work list (taken when the
+    first instance retires, or from the start when tail_active >= n) keep the
+    steps and the fields bitwise."""
+    inst = [dict(nx=16, ny=32, tau=0.9, u_top=0.04, T_top=1.1),
+            dict(nx=40, ny=48, tau=0.6, u_top=0.02, T_top=1.05)]
+    res = []
+    for t in (None, tuning):
+        b = BatchSolver(inst, dtype="f32")
+        if t:
+            b.set_tuning(**t)
+            got = b.tuning()
+            assert all(got[k] == v for k, v in t.items())
+        b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in inst])
+        ok, steps, r = b.run(max_steps=400000, tol=1e-8, k_interval=100)
+        assert ok
+        res.append((steps, b.fields()))
+        b.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    for a, c in zip(res[0][1], res[1][1]):
+        assert np.array_equal(a, c)
+
+
+def test_batch_tuning_rejects_bad_values():
+    b = BatchSolver(INST[:1], dtype="f32")
+    for bad in [dict(prefetch=2), dict(tail_active=-1), dict(tail_width=48), dict(tail_rows=0),
+                dict(tail_rows=256)]:
+        with pytest.raises(Exception):
+            b.set_tuning(**bad)
+    b.close()
