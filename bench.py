@@ -72,7 +72,8 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
     }
 
 
-def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100):
+def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100,
+                solve: bool = True, load_steps: int = 500):
     """Batched steady solves of the thermal-Couette sampler (seed 2026) in one
     persistent, graph-captured run, against plain single-instance solves.
 
@@ -81,28 +82,43 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
     instance of the batch takes exactly as many steps plain as batched (the
     arithmetic is identical, tested bitwise), so the plain wall time of the
     whole batch is the sum over instances of steps x the measured plain time
-    per step of its size (residual checks included)."""
+    per step of its size (residual checks included).
+
+    Before the solve, load_steps steps with every instance active give the
+    batched kernel's full-load throughput; solve=False stops there."""
     import numpy as np
     import torch
 
     from paper_1004_5059_amd import inputs
-    from paper_1004_5059_amd.autotune import autotune_batch
+    from paper_1004_5059_amd.autotune import apply_batch_tuning, autotune, autotune_batch
     from paper_1004_5059_amd.tvlbm import BatchSolver, Solver
 
     insts = inputs.couette_instances(n_inst, seed=2026)
-    shapes = autotune_batch(insts)
+    t0 = time.perf_counter()
+    tune = autotune_batch(insts)
+    t_tune = time.perf_counter() - t0
     b = BatchSolver(insts, dtype="f32")
-    for c, (w, r) in shapes.items():
-        b.set_shape(c, w, r)
+    apply_batch_tuning(b, tune)
     b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
     b.run(2 * k, tol=0.0, k_interval=k)  # warm-up, graph capture
+    cells = np.array([d["nx"] * d["ny"] for d in insts])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(load_steps, tol=0.0, k_interval=k)
+    t_load = (time.perf_counter() - t0) / load_steps
+    load = {"steps": load_steps, "us_per_step": round(t_load * 1e6, 2),
+            "mlups": round(float(cells.sum()) / t_load / 1e6, 1),
+            "achieved_gbs": round(128.0 * float(cells.sum()) / t_load / 1e9, 1)}  # 8Q B/cell
+    if not solve:
+        b.close()
+        return {"instances": n_inst, "full_load": load, "tuning": tune["tuning"],
+                "shapes": {str(c): list(v) for c, v in tune["shapes"].items()}}
     b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ok, steps, r = b.run(5_000_000, tol, k)
     t_batch = time.perf_counter() - t0
     b.close()
-    cells = np.array([d["nx"] * d["ny"] for d in insts])
     # plain: per-size time per step from a stratified sample
     rng = np.random.default_rng(0)
     per_step = {}
@@ -110,11 +126,19 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
     for ny in sorted(set(d["ny"] for d in insts)):
         idx = [i for i, d in enumerate(insts) if d["ny"] == ny]
         pick = rng.choice(idx, min(plain_per_size, len(idx)), replace=False)
+        # the plain path gets its own best launch variant for this size
+        d = insts[idx[0]]
+        probe = Solver(d["nx"], d["ny"], n_gh=4, dtype="f32", tau=d["tau"], walls=True,
+                       wall_lo=(0.0, d["T_bot"]), wall_hi=(d["u_top"], d["T_top"]))
+        probe.set_fields(*inputs.uniform_fields(d["nx"], d["ny"]))
+        variant, _ = autotune(probe, steps=200)
+        probe.close()
         ts, ns = 0.0, 0
         for i in pick:
             d = insts[i]
             s = Solver(d["nx"], d["ny"], n_gh=4, dtype="f32", tau=d["tau"], walls=True,
                        wall_lo=(0.0, d["T_bot"]), wall_hi=(d["u_top"], d["T_top"]))
+            s.set_variant(variant)
             s.set_fields(*inputs.uniform_fields(d["nx"], d["ny"]))
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -134,7 +158,9 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
         "steps_max": int(np.max(steps)), "steps_mean": float(np.mean(steps)),
         "plain_sample": f"{len(sample)} instances ({plain_per_size} per N_y) solved one by one; "
                         "whole-batch plain time = sum of steps x per-size time per step",
-        "shapes": {str(c): list(v) for c, v in shapes.items()},
+        "full_load": load,
+        "shapes": {str(c): list(v) for c, v in tune["shapes"].items()},
+        "tuning": tune["tuning"], "autotune_s": round(t_tune, 2),
     }
 
 
@@ -200,12 +226,16 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="launch variant of the fused step; -1: autotune; default: 0 for D2Q16, "
+                         "5 for D2Q36 (the fastest in the autotuner's sweeps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2q36", action="store_true")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 run")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
+    ap.add_argument("--batched-load-only", action="store_true",
+                    help="batched leg: full-load steps only, no steady solves")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the TVLBM path here is single-GPU "
@@ -218,13 +248,16 @@ def main():
         print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         return r
 
-    r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, args.variant)
+    v16 = 0 if args.variant is None else args.variant
+    v36 = 5 if args.variant is None else args.variant
+    r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, v16)
     r36 = None if args.no_d2q36 else leg("D2Q36", run_lattice, 6, args.size, args.steps,
-                                         args.warmup, args.variant)
+                                         args.warmup, v36)
     big = None if args.no_4096 else leg("D2Q16 4096", run_lattice, 4, 4096,
-                                        max(20, args.steps // 10), 5, args.variant)
+                                        max(20, args.steps // 10), 5, v16)
     cp = None if args.no_copy else leg("copy ceiling", copy_ceiling)
-    bat = None if args.no_batched else leg("batched", run_batched)
+    bat = None if args.no_batched else leg("batched", run_batched, 256, 2, 1e-8, 100,
+                                           not args.batched_load_only)
     cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
     achieved = r16["achieved_gbs"]
     out = {

@@ -65,47 +65,91 @@ def autotune(solver, steps: int = 20, reps: int = 2, cache_path: str | None = No
 
 
 BATCH_SHAPES = [(16, 8), (16, 16), (32, 8), (32, 16), (64, 4), (64, 8)]
+TAIL_SHAPES = [(64, 1), (64, 2), (64, 4), (32, 2)]
 SIZE_CLASSES = [16, 32, 64, 1 << 30]  # max nx of each class
 
 
-def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: str = "f32"):
-    """Per size class (max N_x), pick the (strip width, rows per segment)
-    of the batched kernel by coordinate descent over the classes, timing a
-    fixed number of steps of the whole batch.  Returns {max_nx: (w, rows)}."""
+def apply_batch_tuning(b, tune):
+    """Apply a result of autotune_batch to a BatchSolver."""
+    for c, (w, r) in tune["shapes"].items():
+        b.set_shape(int(c), w, r)
+    b.set_tuning(**tune["tuning"])
+
+
+def _time_steps(b, steps, k_interval):
     import time
 
     import torch
 
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, tol=0.0, k_interval=k_interval)
+    return time.perf_counter() - t0
+
+
+def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: str = "f32",
+                   tail_fraction: float = 0.25):
+    """Launch tuning of the batched solve, timed on the instances themselves.
+
+    Bulk phase (every instance active): the (strip width, rows per segment)
+    of each size class (max N_x) by coordinate descent over the classes,
+    then the prefetch switch.  Tail phase: the single shape used once at
+    most tail_fraction of the instances remain, timed on the instances of
+    the largest N_y (up to 16 of them), which are the last to converge.
+    Returns {"shapes": {max_nx: (w, rows)}, "tuning": {...}}."""
     from . import inputs
     from .tvlbm import BatchSolver
 
-    b = BatchSolver(instances, dtype=dtype)
-    b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in instances])
+    def fresh(insts):
+        b = BatchSolver(insts, dtype=dtype)
+        b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
+        return b
+
+    b = fresh(instances)
     max_nx = max(d["nx"] for d in instances)
-    classes = [c for c in SIZE_CLASSES if c < (1 << 30)] + [1 << 30]
+    classes = list(SIZE_CLASSES)
     choice = {c: (16 if c <= 16 else 32 if c <= 32 else 64, 8) for c in classes}
+    pf = 1
 
     def timed():
         for c, (w, r) in choice.items():
             b.set_shape(c, w, r)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.run(steps, tol=0.0, k_interval=k_interval)
-        return time.perf_counter() - t0
+        b.set_tuning(prefetch=pf)
+        return _time_steps(b, steps, k_interval)
 
     timed()  # warm-up (graph capture)
-    for c in classes:
-        lo = 0 if c == classes[0] else classes[classes.index(c) - 1]
+    for ci, c in enumerate(classes):
+        lo = 0 if ci == 0 else classes[ci - 1]
         if lo >= max_nx:
             continue
         best, best_t = choice[c], float("inf")
         for w, r in BATCH_SHAPES:
-            if w > max(16, c) and c < (1 << 30):
+            if c < (1 << 30) and w > max(16, c):
                 continue
             choice[c] = (w, r)
             t = timed()
             if t < best_t:
                 best, best_t = (w, r), t
         choice[c] = best
+    times = {}
+    for pf in (1, 0):
+        times[pf] = timed()
+    pf = min(times, key=times.get)
     b.close()
-    return choice
+
+    ny_max = max(d["ny"] for d in instances)
+    big = [d for d in instances if d["ny"] == ny_max][:16]
+    tb = fresh(big)
+    tb.set_tuning(prefetch=pf)
+    best, best_t = TAIL_SHAPES[0], float("inf")
+    _time_steps(tb, 2 * k_interval, k_interval)
+    for w, r in TAIL_SHAPES:
+        tb.set_shape(1 << 30, w, r)
+        t = _time_steps(tb, 4 * steps, k_interval)
+        if t < best_t:
+            best, best_t = (w, r), t
+    tb.close()
+    tail_active = max(1, int(len(instances) * tail_fraction))
+    return {"shapes": dict(choice),
+            "tuning": {"prefetch": pf, "tail_active": tail_active, "tail_width": best[0],
+                       "tail_rows": best[1]}}

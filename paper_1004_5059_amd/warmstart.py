@@ -76,11 +76,17 @@ def predicted_fields(insts, y):
     return out
 
 
-def solve_batch(insts, fields=None, max_steps=2_000_000, tol=1e-8, k=100, dtype="f32"):
-    """Batched solve; returns (steps, residuals, profiles, seconds)."""
+def solve_batch(insts, fields=None, max_steps=2_000_000, tol=1e-8, k=100, dtype="f32", tune=None):
+    """Batched solve; returns (steps, residuals, profiles, seconds).  tune: a
+    result of autotune.autotune_batch (launch shapes only; results do not
+    depend on it)."""
     import torch
 
     b = BatchSolver(insts, dtype=dtype)
+    if tune is not None:
+        from .autotune import apply_batch_tuning
+
+        apply_batch_tuning(b, tune)
     if fields is None:
         fields = [inputs.uniform_fields(d["nx"], d["ny"]) for d in insts]
     b.set_fields(fields)
@@ -94,6 +100,7 @@ def solve_batch(insts, fields=None, max_steps=2_000_000, tol=1e-8, k=100, dtype=
 
 
 def generate(n: int, seed: int, batch: int = 256, log=print, **kw):
+    """Steady states of n sampled channels, solved in batches of `batch`."""
     insts = inputs.couette_instances(n, seed=seed)
     profiles, steps = [], []
     for s in range(0, n, batch):
@@ -152,18 +159,18 @@ def init_params(c_in: int, seed: int = 0):
     return np.concatenate(parts).astype(np.float32)
 
 
-def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print):
+def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, tune=None):
     """Solve the same instances from the uniform start and from the network's
     prediction (inference time included); returns a summary dict."""
     import torch
 
-    st_u, r_u, prof_u, t_u = solve_batch(insts, max_steps=max_steps, tol=tol)
+    st_u, r_u, prof_u, t_u = solve_batch(insts, max_steps=max_steps, tol=tol, tune=tune)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     y = predict(net, insts, H, W)
     fields = predicted_fields(insts, y)
     t_inf = time.perf_counter() - t0
-    st_w, r_w, prof_w, t_w = solve_batch(insts, fields=fields, max_steps=max_steps, tol=tol)
+    st_w, r_w, prof_w, t_w = solve_batch(insts, fields=fields, max_steps=max_steps, tol=tol, tune=tune)
     bad = [k for k in range(len(insts)) if not (r_w[k] < tol) or not np.all(np.isfinite(prof_w[k]))]
     t_fb = 0.0
     if bad:
@@ -206,8 +213,12 @@ def main(argv=None):
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     H, W = 256, 128
+    from .autotune import autotune_batch
+
+    tune = autotune_batch(inputs.couette_instances(256, seed=2026))
+    log(f"batch tuning: {tune}")
     t0 = time.perf_counter()
-    tr, prof, steps = generate(a.n_train, seed=2026, log=log)
+    tr, prof, steps = generate(a.n_train, seed=2026, log=log, tune=tune)
     t_gen = time.perf_counter() - t0
     net = TvNet(C_IN, H, W, max_batch=a.batch)
     net.set_params(init_params(C_IN, seed=0))
@@ -217,7 +228,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     te = inputs.couette_instances(a.n_test, seed=2027)
-    res = warm_vs_uniform(net, te, H, W, log=log)
+    res = warm_vs_uniform(net, te, H, W, log=log, tune=tune)
     res.update({"data_generation_s": t_gen, "training_s": t_train, "n_train": a.n_train,
                 "epochs": a.epochs, "final_loss": hist[-1], "train_steps_mean": float(np.mean(steps))})
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
