@@ -31,14 +31,14 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
+def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype: str = "f32"):
     import torch
 
     from paper_1004_5059_amd import inputs
     from paper_1004_5059_amd.autotune import autotune
     from paper_1004_5059_amd.tvlbm import Solver
 
-    s = Solver(size, size, n_gh=n, dtype="f32", tau=0.6, device="cuda:0")
+    s = Solver(size, size, n_gh=n, dtype=dtype, tau=0.6, device="cuda:0")
     s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
     if variant < 0:
         variant, tune = autotune(s, steps=20)
@@ -60,7 +60,8 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int):
     q = n * n
     cells = size * size
     launch_s = ms / 1e3 / steps
-    bytes_per_launch = 8 * q * cells  # one FP32 read + one write per population
+    esz = 4 if dtype == "f32" else 8
+    bytes_per_launch = 2 * esz * q * cells  # one read + one write per population
     return {
         "mlups": cells * steps / (ms / 1e3) / 1e6,
         "ms_per_step": ms / steps,
@@ -164,6 +165,34 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
     }
 
 
+def run_c0(steps: int = 200):
+    """The small latency-bound case: 64 x 64 periodic D2Q16 in FP64, tau 0.8,
+    shear wave u_x = 0.01 sin(2 pi y / 64) plus uniform population noise
+    +-1e-4 (seed 0), 200 steps."""
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.tvlbm import Solver
+
+    s = Solver(64, 64, n_gh=4, dtype="f64", tau=0.8, device="cuda:0")
+    s.set_fields(*inputs.shear_wave_fields(64, 64, eps=0.01),
+                 inputs.population_noise(16, 64, 64, amp=1e-4, seed=0))
+    s.step(5)
+    s.set_fields(*inputs.shear_wave_fields(64, 64, eps=0.01),
+                 inputs.population_noise(16, 64, 64, amp=1e-4, seed=0))
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(steps)
+    b.record(s.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    s.close()
+    return {"steps": steps, "ms": round(ms, 3), "us_per_step": round(ms * 1e3 / steps, 2),
+            "mlups": round(64 * 64 * steps / (ms / 1e3) / 1e6, 1)}
+
+
 def copy_ceiling(mib: int = 1024, reps: int = 10):
     """Device-to-device copy of a buffer larger than the MALL: the achievable
     HBM bandwidth ceiling (bytes read + bytes written per second)."""
@@ -227,12 +256,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--variant", type=int, default=None,
-                    help="launch variant of the fused step; -1: autotune; default: 0 for D2Q16, "
-                         "5 for D2Q36 (the fastest in the autotuner's sweeps)")
+                    help="launch variant of the fused step; -1: autotune; default: 16 for D2Q16 "
+                         "(column pairs, 64 lanes x 2 rows), 10 for D2Q36 (32 x 8), the fastest in "
+                         "the autotuner's sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2q36", action="store_true")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 run")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling measurement")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 lines (1024^2 and 64^2)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
     ap.add_argument("--batched-load-only", action="store_true",
                     help="batched leg: full-load steps only, no steady solves")
@@ -248,13 +279,16 @@ def main():
         print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         return r
 
-    v16 = 0 if args.variant is None else args.variant
-    v36 = 5 if args.variant is None else args.variant
+    v16 = 16 if args.variant is None else args.variant
+    v36 = 10 if args.variant is None else args.variant
     r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, v16)
     r36 = None if args.no_d2q36 else leg("D2Q36", run_lattice, 6, args.size, args.steps,
                                          args.warmup, v36)
     big = None if args.no_4096 else leg("D2Q16 4096", run_lattice, 4, 4096,
                                         max(20, args.steps // 10), 5, v16)
+    r64 = None if args.no_f64 else leg("D2Q16 FP64", run_lattice, 4, args.size, args.steps,
+                                       args.warmup, v16, "f64")
+    c0 = None if args.no_f64 else leg("C0 64x64 FP64", run_c0)
     cp = None if args.no_copy else leg("copy ceiling", copy_ceiling)
     bat = None if args.no_batched else leg("batched", run_batched, 256, 2, 1e-8, 100,
                                            not args.batched_load_only)
@@ -289,6 +323,10 @@ def main():
         "d2q16_4096": None if big is None else {
             "mlups": round(big["mlups"], 1), "achieved_gbs": round(big["achieved_gbs"], 1),
             "frac": round(big["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": big["variant"]},
+        "d2q16_f64": None if r64 is None else {
+            "mlups": round(r64["mlups"], 1), "achieved_gbs": round(r64["achieved_gbs"], 1),
+            "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": r64["variant"]},
+        "c0_64x64_f64": c0,
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
         "batched": bat,
     }

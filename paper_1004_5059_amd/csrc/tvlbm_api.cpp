@@ -22,15 +22,19 @@ using namespace tvlbm;
 namespace {
 
 struct Variant {
-  int width;     // columns per wavefront strip
+  int width;     // columns per wavefront strip (lanes; pairs of columns if `pairs`)
   int rows;      // rows per lane segment
   int prefetch;  // software-pipelined rows
+  int pairs;     // FP32 step on two adjacent columns per lane (8-byte accesses);
+                 // grids it does not apply to run the same shape one column per lane
 };
 // Launch shapes of the fused step; all compute identical results.  Variant
 // 0 is the default.
 const Variant kVariants[] = {{64, 4, 0}, {64, 2, 1}, {64, 8, 1}, {64, 16, 1}, {64, 4, 1},
                              {64, 8, 0}, {32, 8, 1}, {32, 16, 1}, {16, 16, 1}, {64, 2, 0},
-                             {32, 8, 0}};
+                             {32, 8, 0}, {64, 16, 0}, {64, 32, 0}, {32, 16, 0},
+                             {64, 4, 0, 1}, {64, 8, 0, 1}, {64, 2, 0, 1}, {64, 16, 0, 1},
+                             {32, 8, 0, 1}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -229,11 +233,8 @@ static void fill_lat(const HostLattice& H, Lat<R>& L) {
   }
   double sw = 0.0;
   for (int l = 0; l < H.q; ++l) {
-    const double c2 = H.xi[2 * l] * H.xi[2 * l] + H.xi[2 * l + 1] * H.xi[2 * l + 1];
     L.w[l] = (R)H.w[l];
     L.wd[l] = H.w[l];
-    L.cD[l] = (R)(c2 - 2.0);
-    L.c4[l] = (R)((c2 * c2 - 8.0 * c2 + 8.0) / 8.0);
     sw += H.w[l];
   }
   L.sumw = sw;
@@ -348,10 +349,73 @@ template <>
 Inst<double>& inst_of<double>(tvlbm_ctx* c) { return c->instd; }
 
 // Launch the fused kernel in a mode.  src is a population buffer (pitch ld).
+// The column-pair step applies to FP32 grids periodic in y with uniform rows
+// and an even width and pitch.
+static bool pairs_ok(const tvlbm_ctx* c) {
+  return !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC && c->d.nx % 2 == 0 && c->ld % 2 == 0;
+}
+
+static f32x2 splat2(float v) { return f32x2{v, v}; }
+
+// The single-grid step arguments restated in column-pair units.
+static MarchArgs<f32x2> pair_args(const MarchArgs<float>& A) {
+  MarchArgs<f32x2> B;
+  std::memset(&B, 0, sizeof B);
+  for (int k = 0; k < NMAX; ++k) {
+    B.lat.p[k] = splat2(A.lat.p[k]);
+    B.lat.qm[k] = splat2(A.lat.qm[k]);
+    B.lat.x[k] = splat2(A.lat.x[k]);
+    B.lat.x2[k] = splat2(A.lat.x2[k]);
+    B.lat.xd[k] = A.lat.xd[k];
+  }
+  for (int l = 0; l < QMAX; ++l) {
+    B.lat.w[l] = splat2(A.lat.w[l]);
+    B.lat.wd[l] = A.lat.wd[l];
+    B.inst.oww[l] = splat2(A.inst.oww[l]);
+    B.inst.kap_lo[l] = splat2(A.inst.kap_lo[l]);
+    B.inst.phi_lo[l] = splat2(A.inst.phi_lo[l]);
+    B.inst.kap_hi[l] = splat2(A.inst.kap_hi[l]);
+    B.inst.phi_hi[l] = splat2(A.inst.phi_hi[l]);
+  }
+  B.lat.sumw = A.lat.sumw;
+  B.inst.off = A.inst.off / 2;
+  B.inst.plane = A.inst.plane / 2;
+  B.inst.ld = A.inst.ld / 2;
+  B.inst.fld = A.inst.fld;
+  B.inst.nx = A.inst.nx / 2;
+  B.inst.ny = A.inst.ny;
+  B.inst.walls = A.inst.walls;
+  B.inst.id = A.inst.id;
+  B.inst.omo = splat2(A.inst.omo);
+  B.width = A.width;
+  B.rows = A.rows;
+  B.src = (const f32x2*)(const void*)A.src;
+  B.dst = (f32x2*)(void*)A.dst;
+  return B;
+}
+
 template <typename R>
 static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
                      bool want_totals) {
   const Variant v = kVariants[c->variant];
+  if constexpr (std::is_same<R, float>::value) {
+    if (v.pairs && mode == MODE_STEP && pairs_ok(c)) {
+      const Geometry g = geometry(c->d.nx / 2, c->d.ny, v);
+      MarchArgs<float> A;
+      std::memset(&A, 0, sizeof A);
+      A.lat = lat_of<float>(c);
+      A.inst = inst_of<float>(c);
+      A.width = v.width;
+      A.rows = v.rows;
+      A.src = (const float*)src;
+      A.dst = (float*)dst;
+      MarchArgs<f32x2> B = pair_args(A);
+      B.tiles_x = g.tiles_x;
+      B.n_tiles = g.n_tiles;
+      HIPCHK(c, launch_march_pairs(c->hl.n, c->comp, B, g.nblocks, c->st));
+      return TVLBM_OK;
+    }
+  }
   const Geometry g = c->rows ? geometry_rows(c->d.nx, c->d.ny) : geometry(c->d.nx, c->d.ny, v);
   MarchArgs<R> A;
   std::memset(&A, 0, sizeof A);

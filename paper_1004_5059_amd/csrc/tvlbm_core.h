@@ -14,6 +14,16 @@
 
 namespace tvlbm {
 
+// Two FP32 cells per lane: the step kernel can run on a pair of adjacent
+// columns held as a 2-wide vector, with every operation elementwise (so each
+// cell's arithmetic is exactly that of the scalar kernel) and 8-byte loads
+// and stores.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <typename R>
+inline constexpr bool is_pair_v = false;
+template <>
+inline constexpr bool is_pair_v<f32x2> = true;
+
 constexpr int NMAX = 6;   // Gauss-Hermite points per axis
 constexpr int QMAX = 36;  // populations
 constexpr double DIM = 2.0;
@@ -29,8 +39,6 @@ struct Lat {
   R x[NMAX];    // node a (Hermite units)
   R x2[NMAX];   // x_a^2
   R w[QMAX];    // w_l
-  R cD[QMAX];   // |xi_l|^2 - D
-  R c4[QMAX];   // (|xi_l|^4 - 2(D+2)|xi_l|^2 + D(D+2)) / 8
   double xd[NMAX];
   double wd[QMAX];
   double sumw;  // sum of wd
@@ -112,6 +120,9 @@ struct MarchArgs {
 // promote float operands).
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ f32x2 fmaR(f32x2 a, f32x2 b, f32x2 c) {
+  return __builtin_elementwise_fma(a, b, c);
+}
 
 // ------------------------------------------------------ compensation -----
 // Kahan's compensated summation: (s, c) accumulates x with the rounding
@@ -256,82 +267,126 @@ __device__ __forceinline__ Fields<R> fields_from(R drho, R jx, R jy, R ed) {
 // ------------------------------------------------------------ equilibrium --
 // Hermite equilibrium (Sec. II; scalar form of Appendix A) in deviation form:
 //   feq_l - w_l = w_l [ drho + rho P_l ],
-//   P_l = u_l + 1/2 (u_l^2 - u^2 + th cD)
-//       + (u_l / 6)(u_l^2 - 3 u^2 + 3 th (cD - 2))                       [ORD>=3]
-//       + (u_l^4 - 6 u_l^2 u^2 + 3 u^4)/24
-//       + (th/4)((cD - 2)(u_l^2 - u^2) - 2 u_l^2) + th^2 c4              [ORD>=4]
-// with u_l = u.xi_l, th = T - 1, cD = |xi_l|^2 - D and
-// c4 = (|xi_l|^4 - 2(D+2)|xi_l|^2 + D(D+2))/8.  Collecting powers of s = u_l,
-//   P_l = k0 + s (k1 + s (k2 + s (1/6 + s/24)))
-//   k0 = -u^2/2 + (th/2) cD                  [+ u^4/8 + th u^2/2 + th^2 c4 - th u^2 cD/4]
-//   k1 = 1 - u^2/2 - th + (th/2) cD
-//   k2 = 1/2                                 [- u^2/4 - th + th cD/4]
-// (bracketed terms for order 4; order 3 drops the s^4 term; order 2 keeps
-// k0 = -u^2/2 + (th/2) cD, k1 = 1, k2 = 1/2 and no s^3 term).
-template <typename R>
-struct EqCell {
-  R ua[NMAX], vb[NMAX];  // x_a ux, x_b uy
-  R g0, be, al, mu, a2, thq, thsq;
+//   P_l = s + 1/2 (s^2 - u^2 + th (c^2 - D))
+//       + (s / 6)(s^2 - 3 u^2 + 3 th (c^2 - D - 2))                        [ORD>=3]
+//       + (s^4 - 6 s^2 u^2 + 3 u^4)/24
+//       + (th/4)((c^2 - D - 2)(s^2 - u^2) - 2 s^2)
+//       + (th^2/8)(c^4 - 2(D+2) c^2 + D(D+2))                              [ORD>=4]
+// with s = u.xi_l, c = |xi_l|, th = T - 1, D = 2.
+//
+// On the tensor-product set xi_l = (x_a, x_b), P_l is a polynomial of total
+// degree ORD in (x, y) = (x_a, x_b).  Collecting its monomials x^i y^j splits
+// it exactly into terms of one node each (with U = u_x, V = u_y,
+// A2 = (U^2 + th)/2, A3 = U (U^2 + 3 th)/6, B2, B3 likewise in V):
+//   P(x, y) = F(x) + G(y) + y K(x) + x M(y) + N(x) O(y),
+//   K(x) = x (k0 + x (k1 + x k2)),  M(y) = y^2 (m0 + y m1),
+//   N(x) O(y) = A2 x^2 B2 y^2                                      [ORD>=4]
+// with the coefficients of eq_nodes below.  Per cell, the y-node terms G, M,
+// O are evaluated once per node and the x-node terms F, K (scaled by rho,
+// drho folded into F) once per row of the tensor; per population the
+// equilibrium deviation then costs three or four fused operations.
+template <typename R, int N>
+struct EqNodes {
+  R f0, f1, f2, f3, f4, k0, k1, k2, na;  // rho-scaled x-node coefficients
+  R G[N], M[N], Ob[N];                   // y-node terms
 };
 
 template <typename R, int N, int ORD>
-__device__ __forceinline__ EqCell<R> eq_cell(const Lat<R>& L, const Fields<R>& F) {
-  EqCell<R> E;
+__device__ __forceinline__ void eq_nodes(const Lat<R>& L, const Fields<R>& Fd, EqNodes<R, N>& E) {
+  const R U = Fd.ux, V = Fd.uy, th = Fd.th, rho = Fd.rho;
+  const R U2 = U * U, V2 = V * V, u2 = U2 + V2, hth = R(0.5) * th;
+  const R A2 = fmaR(R(0.5), U2, hth), B2 = fmaR(R(0.5), V2, hth);
+  // polynomial coefficients: F = sum f_i x^i, G = sum_{i>=1} g_i y^i
+  R f0, f1, f2, f3 = R(0), f4 = R(0), g1, g2, g3 = R(0), g4 = R(0);
+  R k0, k1 = R(0), k2 = R(0), m0 = R(0), m1 = R(0);
+  if constexpr (ORD == 2) {
+    f0 = -fmaR(R(0.5), u2, th);
+    f1 = U; f2 = A2; g1 = V; g2 = B2;
+    k0 = U * V;
+  } else {
+    const R A3 = U * fmaR(R(3), th, U2) * R(1.0 / 6.0);
+    const R B3 = V * fmaR(R(3), th, V2) * R(1.0 / 6.0);
+    const R mm = R(1) - fmaR(R(0.5), u2, R(2) * th);  // 1 - u^2/2 - 2 th
+    f1 = U * mm; g1 = V * mm;
+    f3 = A3; g3 = B3;
+    k1 = V * A2; m0 = U * B2;
+    if constexpr (ORD == 3) {
+      f0 = -fmaR(R(0.5), u2, th);
+      f2 = A2; g2 = B2;
+      k0 = U * V;
+    } else {
+      const R th2 = th * th;
+      // u^4/8 + th u^2 - u^2/2 + th^2 - th
+      f0 = fmaR(u2, fmaR(R(0.125), u2, th - R(0.5)), th2 - th);
+      // -(U^2 u^2 + 7 U^2 th - 2 U^2 + V^2 th + 4 th^2 - 2 th)/4, and in V
+      const R cth = fmaR(R(4), th2, R(-2) * th);
+      f2 = R(-0.25) * fmaR(U2, u2 + fmaR(R(7), th, R(-2)), fmaR(V2, th, cth));
+      g2 = R(-0.25) * fmaR(V2, u2 + fmaR(R(7), th, R(-2)), fmaR(U2, th, cth));
+      // (U^4 + 6 U^2 th + 3 th^2)/24, and in V
+      f4 = fmaR(U2, U2 + R(6) * th, R(3) * th2) * R(1.0 / 24.0);
+      g4 = fmaR(V2, V2 + R(6) * th, R(3) * th2) * R(1.0 / 24.0);
+      k0 = U * V * (R(1) - fmaR(R(0.5), u2, R(3) * th));
+      k2 = V * A3; m1 = U * B3;
+    }
+  }
+  // scale by rho; drho joins the constant term
+  E.f0 = fmaR(rho, f0, Fd.drho);
+  E.f1 = f1 * rho; E.f2 = f2 * rho; E.f3 = f3 * rho; E.f4 = f4 * rho;
+  E.k0 = k0 * rho; E.k1 = k1 * rho; E.k2 = k2 * rho;
+  E.na = rho * A2;
+  g1 *= rho; g2 *= rho; g3 *= rho; g4 *= rho; m0 *= rho; m1 *= rho;
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    E.ua[a] = L.x[a] * F.ux;
-    E.vb[a] = L.x[a] * F.uy;
+  for (int b = 0; b < N; ++b) {
+    const R y = L.x[b], y2 = L.x2[b];
+    R g = g2;
+    if constexpr (ORD >= 3) {
+      R h = g3;
+      if constexpr (ORD >= 4) h = fmaR(y, g4, h);
+      g = fmaR(y, h, g);
+      E.M[b] = y2 * ((ORD >= 4) ? fmaR(y, m1, m0) : m0);
+    } else {
+      E.M[b] = R(0);
+    }
+    E.G[b] = y * fmaR(y, g, g1);
+    if constexpr (ORD >= 4) E.Ob[b] = B2 * y2;
   }
-  const R u2 = F.ux * F.ux + F.uy * F.uy;
-  const R th = F.th;
-  E.be = R(0.5) * th;
-  E.thq = R(0.25) * th;
-  E.thsq = th * th;
-  if constexpr (ORD >= 3) {
-    E.al = R(1) - R(0.5) * u2 - th;
-  } else {
-    E.al = R(1);
-  }
-  if constexpr (ORD >= 4) {
-    E.g0 = -R(0.5) * u2 + u2 * (R(0.125) * u2 + E.be);
-    E.mu = E.be - E.thq * u2;
-    E.a2 = R(0.5) - R(0.25) * u2 - th;
-  } else {
-    E.g0 = -R(0.5) * u2;
-    E.mu = E.be;
-    E.a2 = R(0.5);
-  }
-  return E;
 }
 
-// returns P_l (the equilibrium polynomial minus its leading 1)
+// x-node terms of node a: F(x_a) (rho-scaled, drho folded in), K(x_a) and
+// the rho A2 x_a^2 factor of the order-4 cross term
 template <typename R, int N, int ORD>
-__device__ __forceinline__ R eq_poly(const Lat<R>& L, const EqCell<R>& E, int a, int b) {
-  const int l = a * N + b;
-  const R s = E.ua[a] + E.vb[b];
-  const R cD = L.cD[l];
-  R k0 = fmaR(cD, E.mu, E.g0);
-  if constexpr (ORD >= 4) k0 = fmaR(E.thsq, L.c4[l], k0);
-  const R k1 = (ORD >= 3) ? fmaR(cD, E.be, E.al) : E.al;
-  R h;
-  if constexpr (ORD >= 4) {
-    const R k2 = fmaR(cD, E.thq, E.a2);
-    h = fmaR(s, R(1.0 / 24.0), R(1.0 / 6.0));
-    h = fmaR(s, h, k2);
-  } else if constexpr (ORD == 3) {
-    h = fmaR(s, R(1.0 / 6.0), E.a2);
-  } else {
-    h = E.a2;
+__device__ __forceinline__ void eq_anode(const Lat<R>& L, const EqNodes<R, N>& E, int a, R& Fa,
+                                         R& Ka, R& Na) {
+  const R x = L.x[a];
+  R f = E.f2, k = E.k0;
+  if constexpr (ORD >= 3) {
+    R t = E.f3;
+    if constexpr (ORD >= 4) t = fmaR(x, E.f4, t);
+    f = fmaR(x, t, f);
+    k = fmaR(x, (ORD >= 4) ? fmaR(x, E.k2, E.k1) : E.k1, k);
   }
-  h = fmaR(s, h, k1);
-  return fmaR(s, h, k0);
+  Fa = fmaR(x, fmaR(x, f, E.f1), E.f0);
+  Ka = x * k;
+  Na = (ORD >= 4) ? E.na * L.x2[a] : R(0);
+}
+
+// drho + rho P_l for population l = (a, b), given node a's terms
+template <typename R, int N, int ORD>
+__device__ __forceinline__ R eq_dev(const Lat<R>& L, const EqNodes<R, N>& E, int a, int b, R Fa,
+                                    R Ka, R Na) {
+  R e = Fa + E.G[b];
+  e = fmaR(L.x[b], Ka, e);
+  if constexpr (ORD >= 3) e = fmaR(L.x[a], E.M[b], e);
+  if constexpr (ORD >= 4) e = fmaR(Na, E.Ob[b], e);
+  return e;
 }
 
 // BGK update in deviation form (eq.(lb) integrated over one step, tau in
-// steps):  d* = d + (feq_dev - d)/tau = (1 - 1/tau) d + (w/tau)(drho + rho P).
+// steps):  d* = d + (feq_dev - d)/tau = (1 - 1/tau) d + (w/tau) e,
+// e = drho + rho P.
 template <typename R>
-__device__ __forceinline__ R bgk(R d, R oww_l, R omo, R rho, R drho, R P) {
-  return fmaR(oww_l, fmaR(rho, P, drho), omo * d);
+__device__ __forceinline__ R bgk(R d, R oww_l, R omo, R e) {
+  return fmaR(oww_l, e, omo * d);
 }
 
 }  // namespace tvlbm

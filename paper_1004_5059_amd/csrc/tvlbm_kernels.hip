@@ -58,6 +58,15 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, double x) 
   using v2i = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, x), r, v * 8u, s * 8u, 0);
 }
+// column pairs: offsets count pairs (8 bytes)
+template <>
+__device__ __forceinline__ f32x2 bld<f32x2>(rsrc_t r, uint32_t v, uint32_t s) {
+  return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8u, s * 8u, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, f32x2 x) {
+  using v2i = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, x), r, v * 8u, s * 8u, 0);
+}
 
 // Lane offsets of one row: centre, left and right neighbour (periodic in x).
 struct RowOff {
@@ -73,9 +82,23 @@ template <typename R, int N>
 __device__ __forceinline__ R xpull(const Lat<R>& L, rsrc_t s, uint32_t lo, int a, const RowOff& o) {
   const int sg = node_sign<N>(a);
   R vc = bld<R>(s, o.c, lo);
-  if (sg > 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.m, lo));
-  if (sg < 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.p, lo));
-  return vc;
+  if constexpr (is_pair_v<R>) {
+    // lane holds columns (2k, 2k+1); the upstream neighbours are (2k-1, 2k)
+    // or (2k+1, 2k+2): one half from the adjacent pair, one from this one
+    if (sg > 0) {
+      const R m = bld<R>(s, o.m, lo);
+      return fmaR(L.qm[a], vc, L.p[a] * R{m.y, vc.x});
+    }
+    if (sg < 0) {
+      const R q = bld<R>(s, o.p, lo);
+      return fmaR(L.qm[a], vc, L.p[a] * R{vc.y, q.x});
+    }
+    return vc;
+  } else {
+    if (sg > 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.m, lo));
+    if (sg < 0) return fmaR(L.qm[a], vc, L.p[a] * bld<R>(s, o.p, lo));
+    return vc;
+  }
 }
 
 // Deviation part of the mass (per unit column width) that the populations
@@ -164,14 +187,16 @@ __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& 
     if (!(A.aux & AUX_POST)) return;
   }
 
-  const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
+  EqNodes<R, N> E;
+  eq_nodes<R, N, ORD>(L, F, E);
 #pragma unroll
   for (int a = 0; a < N; ++a) {
+    R Fa, Ka, Na;
+    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const int l = a * N + b;
-      const R Pl = eq_poly<R, N, ORD>(L, E, a, b);
-      const R g = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, Pl);
+      const R g = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
       if (active) {
         if constexpr (MODE == MODE_AUX) {
           const int64_t op = (int64_t)nx * ny;
@@ -324,8 +349,9 @@ __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& 
   const int jf = DIR > 0 ? j0 : j1 - 1;         // first row visited
   const int jl = DIR > 0 ? j1 - 1 : j0;         // last row visited
   // a wall lies before the first row / after the last row
-  const bool wall_first = P.walls && (DIR > 0 ? j0 == 0 : j1 == ny);
-  const bool wall_last = P.walls && (DIR > 0 ? j1 == ny : j0 == 0);
+  // (column pairs run only on grids periodic in y)
+  const bool wall_first = !is_pair_v<R> && P.walls && (DIR > 0 ? j0 == 0 : j1 == ny);
+  const bool wall_last = !is_pair_v<R> && P.walls && (DIR > 0 ? j1 == ny : j0 == 0);
 
   R hp[Q];
   if (!ident) {
@@ -716,15 +742,19 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
     F.ux = A.ux[c];
     F.uy = A.uy[c];
     F.th = A.T[c] - R(1);
-    const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
+    EqNodes<R, N> E;
+    eq_nodes<R, N, ORD>(L, F, E);
 #pragma unroll
-    for (int a = 0; a < N; ++a)
+    for (int a = 0; a < N; ++a) {
+      R Fa, Ka, Na;
+      eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         const int l = a * N + b;
-        d[l] = L.w[l] * fmaR(F.rho, eq_poly<R, N, ORD>(L, E, a, b), F.drho);
+        d[l] = L.w[l] * eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na);
         if (A.noise) d[l] += A.noise[l * n + c];
       }
+    }
   }
   const int64_t o = P.off + (int64_t)j * P.ld + i;
 #pragma unroll
@@ -732,14 +762,18 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
-  const EqCell<R> E = eq_cell<R, N, ORD>(L, F);
+  EqNodes<R, N> E;
+  eq_nodes<R, N, ORD>(L, F, E);
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+  for (int a = 0; a < N; ++a) {
+    R Fa, Ka, Na;
+    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const int l = a * N + b;
-      A.g0[o + l * P.plane] = bgk(d[l], P.oww[l], P.omo, F.rho, F.drho, eq_poly<R, N, ORD>(L, E, a, b));
+      A.g0[o + l * P.plane] = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
     }
+  }
 }
 
 // ------------------------------------------------------------ reductions --
@@ -829,6 +863,22 @@ hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, 
                         hipStream_t st) {
   (void)comp;
   return march_lat<double, false>(n, mode, A, nblocks, st);
+}
+
+template <bool COMP>
+static hipError_t march_pairs_lat(int n, const MarchArgs<f32x2>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (n) {
+    case 3: hipLaunchKernelGGL((k_march<f32x2, 3, 2, COMP, MODE_STEP, false>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_march<f32x2, 4, 3, COMP, MODE_STEP, false>), g, b, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((k_march<f32x2, 6, 4, COMP, MODE_STEP, false>), g, b, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_march_pairs(int n, bool comp, const MarchArgs<f32x2>& A, int nblocks,
+                              hipStream_t st) {
+  return comp ? march_pairs_lat<true>(n, A, nblocks, st) : march_pairs_lat<false>(n, A, nblocks, st);
 }
 
 template <typename R, bool COMP>

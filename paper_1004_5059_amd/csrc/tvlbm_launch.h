@@ -38,6 +38,10 @@ struct BatchCtl {
 // Workgroups per instance in the batched residual's first pass.
 constexpr int RESID_SLICES = 16;
 
+// Step mode on column pairs (FP32, grid periodic in y, even width and pitch):
+// A describes the grid in pair units (nx, ld, plane halved).
+hipError_t launch_march_pairs(int n, bool comp, const MarchArgs<f32x2>& A, int nblocks,
+                              hipStream_t st);
 // prefetch selects the software-pipelined row loads for the step modes.
 hipError_t launch_march_batch(int n, bool comp, int mode, bool prefetch, const MarchArgs<float>& A,
                               int nblocks, hipStream_t st);
