@@ -255,10 +255,11 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--variant", type=int, default=None,
-                    help="launch variant of the fused step; -1: autotune; default: 16 for D2Q16 "
-                         "(column pairs, 64 lanes x 2 rows), 10 for D2Q36 (32 x 8), the fastest in "
-                         "the autotuner's sweeps")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="launch variant of the D2Q16 fused step (1024^2, 4096^2, FP64); "
+                         "-1 (default): the autotuner's choice on this GPU")
+    ap.add_argument("--variant36", type=int, default=-1,
+                    help="launch variant of the D2Q36 step; -1 (default): autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2q36", action="store_true")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 run")
@@ -279,8 +280,7 @@ def main():
         print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         return r
 
-    v16 = 16 if args.variant is None else args.variant
-    v36 = 10 if args.variant is None else args.variant
+    v16, v36 = args.variant, args.variant36
     r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, v16)
     r36 = None if args.no_d2q36 else leg("D2Q36", run_lattice, 6, args.size, args.steps,
                                          args.warmup, v36)
