@@ -131,6 +131,13 @@ int tvlbm_step_count(const tvlbm_ctx *ctx, int64_t *k);
  * shift[2q] (cells per step, as used by the kernels), lambda. */
 int tvlbm_lattice(const tvlbm_ctx *ctx, double *xi, double *w, double *shift,
                   double *lambda);
+/* The same tables without a context (host only, no device call): the
+ * tensor product of the n_gh-point Gauss-Hermite rule (Sec. II, Appendix A)
+ * that tvlbm_init would build for (n_gh, eq_order, cfl, cfl_norm).  Any
+ * output may be NULL; xi and shift hold 2 n_gh^2 values, w n_gh^2.
+ * EUNSUPPORTED for lattices the kernels do not implement. */
+int tvlbm_lattice_table(int32_t n_gh, int32_t eq_order, double cfl, int32_t cfl_norm,
+                        double *xi, double *w, double *shift, double *lambda);
 
 /* Checkpoint: header + raw state; tvlbm_load needs an identical descriptor. */
 int tvlbm_save(tvlbm_ctx *ctx, const char *path);

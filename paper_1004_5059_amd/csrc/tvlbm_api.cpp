@@ -742,6 +742,18 @@ int tvlbm_lattice(const tvlbm_ctx* c, double* xi, double* w, double* shift, doub
   return TVLBM_OK;
 }
 
+int tvlbm_lattice_table(int32_t n_gh, int32_t eq_order, double cfl, int32_t cfl_norm, double* xi,
+                        double* w, double* shift, double* lambda) {
+  HostLattice hl;
+  if (!build_lattice(n_gh, eq_order, cfl, cfl_norm, &hl)) return TVLBM_EUNSUPPORTED;
+  const int q = hl.q;
+  if (xi) std::memcpy(xi, hl.xi, sizeof(double) * 2 * q);
+  if (w) std::memcpy(w, hl.w, sizeof(double) * q);
+  if (shift) std::memcpy(shift, hl.shift, sizeof(double) * 2 * q);
+  if (lambda) *lambda = hl.lambda;
+  return TVLBM_OK;
+}
+
 int tvlbm_set_variant(tvlbm_ctx* c, int32_t v) {
   if (!c || v < 0 || v >= kNumVariants) return fail(c, TVLBM_EINVAL, "variant");
   c->variant = v;

@@ -34,7 +34,9 @@ bool gauss_hermite_rule(int n, double* x, double* w) {
     const double cx = -lim + 2.0 * lim * s / steps;
     double ch;
     he_pair(n, cx, &ch, &tmp);
-    if (ch == 0.0 || (ch < 0.0) != (prev_h < 0.0)) {
+    if (ch == 0.0) {
+      x[found++] = cx;  // a root on the scan grid (x = 0 for odd n)
+    } else if (prev_h != 0.0 && (ch < 0.0) != (prev_h < 0.0)) {
       double lo = prev_x, hi = cx, hlo = prev_h;
       for (int it = 0; it < 200; ++it) {
         const double mid = 0.5 * (lo + hi);

@@ -127,6 +127,8 @@ def lib():
         "tvlbm_solve": [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _i64p, _dp],
         "tvlbm_step_count": [_vp, _i64p],
         "tvlbm_lattice": [_vp, _dp, _dp, _dp, _dp],
+        "tvlbm_lattice_table": [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                _dp, _dp, _dp, _dp],
         "tvlbm_save": [_vp, ctypes.c_char_p],
         "tvlbm_load": [_vp, ctypes.c_char_p],
         "tvlbm_num_variants": [],
@@ -246,6 +248,17 @@ def tvlbm_lattice(ctx, q: int):
     sh = (ctypes.c_double * (2 * q))()
     lam = ctypes.c_double()
     _check(lib().tvlbm_lattice(ctx, xi, w, sh, ctypes.byref(lam)), ctx)
+    return (np.array(xi[:]).reshape(q, 2), np.array(w[:]), np.array(sh[:]).reshape(q, 2), lam.value)
+
+
+def tvlbm_lattice_table(n_gh: int, eq_order: int, cfl: float = 0.9, cfl_norm: int = 0):
+    """Host-only lattice tables: (xi [q][2], w [q], shift [q][2], lambda)."""
+    q = n_gh * n_gh
+    xi = (ctypes.c_double * (2 * q))()
+    w = (ctypes.c_double * q)()
+    sh = (ctypes.c_double * (2 * q))()
+    lam = ctypes.c_double()
+    _check(lib().tvlbm_lattice_table(n_gh, eq_order, cfl, cfl_norm, xi, w, sh, ctypes.byref(lam)))
     return (np.array(xi[:]).reshape(q, 2), np.array(w[:]), np.array(sh[:]).reshape(q, 2), lam.value)
 
 

@@ -137,14 +137,16 @@ def test_run_to_run_deterministic():
     assert np.array_equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("n", [4, 6])
-def test_c1_full_size_sampled_cells(n):
+# launch variants bench.py's autotuner picks at 1024^2: one column per lane
+# (0: 64 x 4, 5: 64 x 8, 10: 32 x 8) and column pairs (14: 64 x 4, 16: 64 x 2)
+@pytest.mark.parametrize("n,variant", [(4, 0), (4, 14), (4, 16), (6, 5), (6, 10), (6, 14)])
+def test_c1_full_size_sampled_cells(n, variant):
     """1024x1024 periodic, FP32, tau 0.6, smoothed-density init, in the
-    benchmark's launch configuration; 20 steps.  Each sampled cell is
+    benchmark's launch configurations; 20 steps.  Each sampled cell is
     checked against the oracle run on a periodic window around it whose
     half-width exceeds the 20-cell domain of dependence."""
     N, K = 1024, 20
-    s, _ = make_pair(N, N, n=n, dtype="f32", tau=0.6)
+    s, _ = make_pair(N, N, n=n, dtype="f32", tau=0.6, variant=variant)
     fields = inputs.smoothed_density_fields(N, N, std=0.01, t_amp=0.05, seed=1)
     s.set_fields(*fields)
     _, tot0 = s.moments()

@@ -1,0 +1,165 @@
+"""Argument checks of the C ABI that run before any device call: every
+invalid descriptor is rejected with the documented error code (host only, no
+GPU needed)."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_1004_5059_amd import tvlbm as T
+
+pytestmark = pytest.mark.skipif(not os.path.exists(T.LIB_PATH), reason="library not built")
+
+# stand-in device addresses: the checks below reject the descriptor before
+# anything is dereferenced or allocated
+FA, FB = 0x100000, 0x200000
+
+
+def _desc(**kw):
+    d = T.tvlbm_desc()
+    d.n_gh, d.eq_order, d.dtype = 4, 3, T.TVLBM_F32
+    d.nx, d.ny, d.ld = 64, 48, 0
+    d.tau, d.cfl, d.cfl_norm = 0.8, 0.9, 0
+    d.collide, d.y_bc, d.compensated, d.reserved = 1, T.TVLBM_BC_PERIODIC, 1, 0
+    d.wall_lo_T = d.wall_hi_T = 1.0
+    d.f_a, d.f_b = FA, FB
+    d.dy = None
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def _code(fn, *a):
+    with pytest.raises(T.TvlbmError) as e:
+        fn(*a)
+    return e.value.code
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")),
+    dict(nx=1), dict(ny=1), dict(nx=0), dict(nx=-5),
+    dict(dtype=7), dict(y_bc=3), dict(reserved=1),
+    dict(f_a=None), dict(f_b=None), dict(f_b=FA),
+    dict(ld=32),  # pitch below the width
+])
+def test_init_rejects_invalid_descriptors(kw):
+    assert _code(T.tvlbm_init, _desc(**kw)) == T.TVLBM_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(n_gh=5), dict(n_gh=2), dict(n_gh=4, eq_order=5),
+                                dict(n_gh=6, eq_order=2)])
+def test_init_rejects_unsupported_lattices(kw):
+    assert _code(T.tvlbm_init, _desc(**kw)) == T.TVLBM_EUNSUPPORTED
+
+
+def test_init_rejects_population_blocks_of_4_gib():
+    # 36 x 8192 x 8192 FP32 populations = 9.7 GB, beyond the 32-bit buffer offsets
+    d = _desc(n_gh=6, eq_order=4, nx=8192, ny=8192)
+    assert _code(T.tvlbm_init, d) == T.TVLBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_init_rejects_bad_row_heights(bad):
+    dy = (ctypes.c_double * 48)(*([1.0] * 47 + [bad]))
+    d = _desc(dy=ctypes.cast(dy, ctypes.POINTER(ctypes.c_double)))
+    assert _code(T.tvlbm_init, d) == T.TVLBM_EINVAL
+
+
+def test_null_handles_are_rejected():
+    L = T.lib()
+    assert L.tvlbm_step(None, 1) == T.TVLBM_EINVAL
+    assert L.tvlbm_destroy(None) == T.TVLBM_EINVAL
+    assert L.tvlbm_set_variant(None, 0) == T.TVLBM_EINVAL
+    assert L.tvlbm_batch_destroy(None) == T.TVLBM_EINVAL
+    assert L.tvlbm_batch_set_tuning(None, None) == T.TVLBM_EINVAL
+    assert L.tvlbm_init(None, None) == T.TVLBM_EINVAL
+
+
+def test_every_error_code_has_a_message():
+    for code in (T.TVLBM_OK, T.TVLBM_EINVAL, T.TVLBM_EHIP, T.TVLBM_ENOMEM, T.TVLBM_ENONFINITE,
+                 T.TVLBM_EUNSUPPORTED, T.TVLBM_ENOTCONVERGED, T.TVLBM_EIO):
+        msg = T.tvlbm_strerror(code)
+        assert msg and msg != "unknown error", code
+    assert T.tvlbm_strerror(-99) == "unknown error"
+
+
+def _batch(insts, n_gh=4):
+    arr = (T.tvlbm_inst * len(insts))()
+    for k, (nx, ny, tau) in enumerate(insts):
+        arr[k].nx, arr[k].ny, arr[k].tau = nx, ny, tau
+        arr[k].wall_lo_T = arr[k].wall_hi_T = 1.0
+    d = T.tvlbm_batch_desc()
+    d.n_gh, d.eq_order, d.dtype, d.compensated = n_gh, T.LATTICE_ORDER.get(n_gh, 3), T.TVLBM_F32, 1
+    d.cfl, d.cfl_norm, d.n_inst = 0.9, 0, len(insts)
+    d.inst = ctypes.cast(arr, ctypes.POINTER(T.tvlbm_inst))
+    d.arena_a, d.arena_b, d.stream = FA, FB, 0x300000
+    d._keep = arr
+    return d
+
+
+def test_batch_sizes_are_the_packed_layout():
+    # blocks [q][ny][round16(nx)], each 64-element aligned; fields [4][ny][nx]
+    d = _batch([(16, 32, 0.6), (24, 48, 0.9), (100, 20, 0.7)])
+    pop, fld = T.tvlbm_batch_sizes(d)
+    blocks = [16 * 32 * 16, 16 * 48 * 32, 16 * 20 * 112]
+    expect = 0
+    for b in blocks:
+        expect = (expect + b + 63) // 64 * 64
+    assert pop == expect
+    assert fld == 4 * (16 * 32 + 24 * 48 + 100 * 20)
+
+
+@pytest.mark.parametrize("insts,code", [
+    ([(1, 32, 0.6)], T.TVLBM_EINVAL),          # width below 2
+    ([(16, 1, 0.6)], T.TVLBM_EINVAL),          # height below 2
+    ([(65536, 4096, 0.6)], T.TVLBM_EINVAL),    # instance block of 4 GiB or more
+])
+def test_batch_sizes_reject_invalid_instances(insts, code):
+    assert _code(T.tvlbm_batch_sizes, _batch(insts)) == code
+
+
+def test_batch_rejects_unsupported_lattice_and_bad_tau():
+    assert _code(T.tvlbm_batch_sizes, _batch([(16, 32, 0.6)], n_gh=5)) == T.TVLBM_EUNSUPPORTED
+    d = _batch([(16, 32, 0.5)])
+    assert _code(T.tvlbm_batch_init, d) == T.TVLBM_EINVAL
+
+
+def test_batch_init_rejects_shared_or_missing_arenas():
+    d = _batch([(16, 32, 0.6)])
+    d.arena_b = d.arena_a
+    assert _code(T.tvlbm_batch_init, d) == T.TVLBM_EINVAL
+    d = _batch([(16, 32, 0.6)])
+    d.stream = None  # graph capture needs a stream of its own
+    assert _code(T.tvlbm_batch_init, d) == T.TVLBM_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(c_in=0), dict(c_in=9), dict(width=16), dict(c_out=0),
+                                dict(cols=257), dict(height=0), dict(max_batch=0)])
+def test_network_init_rejects_unsupported_shapes(kw):
+    d = T.tvnet_desc()
+    d.c_in, d.width, d.c_out, d.height, d.cols, d.max_batch = 6, 32, 4, 64, 32, 2
+    for k, v in kw.items():
+        setattr(d, k, v)
+    assert _code(T.tvnet_init, d) == T.TVLBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("n,order", [(3, 2), (4, 3), (6, 4)])
+@pytest.mark.parametrize("cfl,norm", [(0.9, 0), (1.0, 1), (0.5, 0)])
+def test_host_lattice_tables_match_the_oracle(n, order, cfl, norm):
+    """The library's Gauss-Hermite tables (its own root finder) against the
+    oracle's (Golub-Welsch): nodes, weights, displacements and lambda."""
+    from oracle import oracle as orc
+
+    xi, w, shift, lam = T.tvlbm_lattice_table(n, order, cfl, norm)
+    ref = orc.OracleLattice(n, order, cfl=cfl, cfl_norm=norm)
+    assert np.allclose(xi, ref.xi, rtol=0, atol=1e-13)
+    assert np.allclose(w, ref.w, rtol=1e-13, atol=0)
+    assert np.allclose(shift, ref.s, rtol=0, atol=1e-13)
+    assert abs(lam - ref.lam) <= 1e-14 * lam
+    assert abs(w.sum() - 1.0) <= 1e-14
+
+
+def test_lattice_table_rejects_unsupported():
+    assert _code(T.tvlbm_lattice_table, 5, 3) == T.TVLBM_EUNSUPPORTED
+    assert _code(T.tvlbm_lattice_table, 4, 3, 0.0) == T.TVLBM_EUNSUPPORTED
