@@ -15,6 +15,14 @@ canvases):
      warm-started solve fails to converge (or goes non-finite) are re-solved
      from the uniform start.
 
+Output parametrisation: with residual=True the network predicts the
+difference between the steady fields and the closed-form thermal Couette
+profile of the instance's parameters (u = U y/H, T = T_b + dT y/H +
+U^2/(2 c_P) (y/H)(1 - y/H), uniform pressure rho T, c_P = 2), scaled by the
+per-channel spread of that difference over the training set; the profile is
+added back to the prediction.  The profile alone, used as a start, is
+reported as a second baseline.
+
 The canvas is H x W = (max N_y) x (max N_x); instance k occupies rows
 0..ny-1 and columns 0..nx-1.
 """
@@ -54,25 +62,66 @@ def canvas_inputs(insts, H: int, W: int):
     return x, mask
 
 
-def canvas_targets(insts, profiles, H: int, W: int):
+def closed_form_profile(d):
+    """[4][ny] closed-form steady thermal Couette profile (rho, ux, uy, T) at
+    the row centres, rho from uniform pressure with unit mean."""
+    ny = d["ny"]
+    y = (np.arange(ny) + 0.5) / ny
+    U = d.get("u_top", 0.0)
+    Tb, Tt = d.get("T_bot", 1.0), d.get("T_top", 1.0)
+    T = Tb + (Tt - Tb) * y + U * U / 4.0 * y * (1.0 - y)
+    rho = (1.0 / T) / np.mean(1.0 / T)
+    return np.stack([rho, U * y, np.zeros(ny), T])
+
+
+def make_param(insts=None, profiles=None, residual=True):
+    """Output parametrisation: offsets and scales of the network's channels
+    (fixed constants, or the closed-form profile and the spread of the
+    residual over the training set)."""
+    if not residual:
+        return {"residual": False, "scale": OUT_SCALE.copy()}
+    res = np.concatenate([(p - closed_form_profile(d)).T for d, p in zip(insts, profiles)])
+    scale = np.maximum(res.std(axis=0), 1e-6)
+    return {"residual": True, "scale": scale}
+
+
+def _offset(d, param):
+    if param["residual"]:
+        return closed_form_profile(d).T  # [ny][4]
+    return np.broadcast_to(OUT_OFFSET, (d["ny"], 4))
+
+
+def canvas_targets(insts, profiles, H: int, W: int, param=None):
     """Normalised steady fields on the canvas from column profiles [4][ny]."""
+    param = param or make_param(residual=False)
     t = np.zeros((len(insts), H, W, 4), dtype=np.float32)
     for k, (d, p) in enumerate(zip(insts, profiles)):
         ny, nx = d["ny"], d["nx"]
-        t[k, :ny, :nx, :] = ((p.T - OUT_OFFSET) / OUT_SCALE)[:, None, :]
+        t[k, :ny, :nx, :] = ((p.T - _offset(d, param)) / param["scale"])[:, None, :]
     return t
 
 
-def predicted_fields(insts, y):
+def predicted_fields(insts, y, param=None):
     """Network output [B][H][W][4] -> per-instance (rho, ux, uy, T) arrays,
     with rho rescaled to unit mean."""
+    param = param or make_param(residual=False)
     out = []
     for k, d in enumerate(insts):
         ny, nx = d["ny"], d["nx"]
-        f = y[k, :ny, :nx, :].astype(np.float64) * OUT_SCALE + OUT_OFFSET
+        f = y[k, :ny, :nx, :].astype(np.float64) * param["scale"] + _offset(d, param)[:, None, :]
         rho = f[..., 0] / f[..., 0].mean()
         T = np.clip(f[..., 3], 0.5, 2.0)
         out.append((rho, f[..., 1], f[..., 2], T))
+    return out
+
+
+def closed_form_fields(insts):
+    """The closed-form profiles as (rho, ux, uy, T) fields, a start without
+    learning."""
+    out = []
+    for d in insts:
+        p = closed_form_profile(d)
+        out.append(tuple(np.repeat(p[c][:, None], d["nx"], axis=1) for c in range(4)))
     return out
 
 
@@ -112,11 +161,11 @@ def generate(n: int, seed: int, batch: int = 256, log=print, **kw):
     return insts, profiles, np.array(steps)
 
 
-def train(net, insts, profiles, H, W, epochs=30, batch=32, lr=2e-3, seed=0, log=print):
+def train(net, insts, profiles, H, W, epochs=30, batch=32, lr=2e-3, seed=0, log=print, param=None):
     import torch
 
     x, mask = canvas_inputs(insts, H, W)
-    t = canvas_targets(insts, profiles, H, W)
+    t = canvas_targets(insts, profiles, H, W, param)
     rng = np.random.default_rng(seed)
     n = len(insts)
     hist = []
@@ -159,16 +208,20 @@ def init_params(c_in: int, seed: int = 0):
     return np.concatenate(parts).astype(np.float32)
 
 
-def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, tune=None):
-    """Solve the same instances from the uniform start and from the network's
-    prediction (inference time included); returns a summary dict."""
+def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, tune=None,
+                    param=None):
+    """Solve the same instances from the uniform start, from the closed-form
+    profile and from the network's prediction (inference time included);
+    returns a summary dict."""
     import torch
 
     st_u, r_u, prof_u, t_u = solve_batch(insts, max_steps=max_steps, tol=tol, tune=tune)
+    st_c, r_c, _, t_c = solve_batch(insts, fields=closed_form_fields(insts), max_steps=max_steps,
+                                    tol=tol, tune=tune)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     y = predict(net, insts, H, W)
-    fields = predicted_fields(insts, y)
+    fields = predicted_fields(insts, y, param)
     t_inf = time.perf_counter() - t0
     st_w, r_w, prof_w, t_w = solve_batch(insts, fields=fields, max_steps=max_steps, tol=tol, tune=tune)
     bad = [k for k in range(len(insts)) if not (r_w[k] < tol) or not np.all(np.isfinite(prof_w[k]))]
@@ -180,10 +233,14 @@ def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, 
             st_w[k] += st_f[j]
             prof_w[k] = prof_f[j]
     err = [float(np.max(np.abs(pw - pu))) for pw, pu in zip(prof_w, prof_u)]
-    pred_err = []
+    pred_err, pred_err_T, cf_err = [], [], []
     for k, d in enumerate(insts):
         pf = np.stack([a[:, 0] for a in fields[k]])
         pred_err.append(float(np.max(np.abs(pf[1] - prof_u[k][1])) / max(d["u_top"], 1e-3)))
+        dT = max(d.get("T_top", 1.0) - d.get("T_bot", 1.0), 1e-3)
+        pred_err_T.append(float(np.max(np.abs(pf[3] - prof_u[k][3])) / dT))
+        cf = closed_form_profile(d)
+        cf_err.append(float(np.max(np.abs(cf[1] - prof_u[k][1])) / max(d["u_top"], 1e-3)))
     out = {
         "n": len(insts),
         "uniform_steps_mean": float(np.mean(st_u)), "warm_steps_mean": float(np.mean(st_w)),
@@ -191,6 +248,11 @@ def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, 
         "uniform_wall_s": t_u, "warm_wall_s": t_w + t_inf + t_fb, "inference_s": t_inf,
         "fallbacks": len(bad), "steady_field_maxdiff": float(np.max(err)),
         "pred_u_err_rel_median": float(np.median(pred_err)),
+        "pred_T_err_rel_median": float(np.median(pred_err_T)),
+        "closed_form_u_err_rel_median": float(np.median(cf_err)),
+        "closed_form_steps_mean": float(np.mean(st_c)), "closed_form_steps_max": int(np.max(st_c)),
+        "closed_form_wall_s": t_c, "closed_form_converged": bool(np.all(r_c < tol)),
+        "speedup_steps_vs_closed_form": float(np.mean(st_c) / np.mean(st_w)),
         "speedup_steps": float(np.mean(st_u) / np.mean(st_w)),
         "speedup_wall": float(t_u / (t_w + t_inf + t_fb)),
     }
@@ -209,7 +271,10 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--out", default="gpurun_out/warmstart.json")
+    ap.add_argument("--out", default="warmstart_result.json")
+    ap.add_argument("--absolute", action="store_true",
+                    help="predict the fields themselves instead of the residual from the "
+                         "closed-form profile")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     H, W = 256, 128
@@ -220,17 +285,20 @@ def main(argv=None):
     t0 = time.perf_counter()
     tr, prof, steps = generate(a.n_train, seed=2026, log=log, tune=tune)
     t_gen = time.perf_counter() - t0
+    param = make_param(tr, prof, residual=not a.absolute)
+    log(f"output parametrisation: residual={param['residual']} scale={param['scale'].tolist()}")
     net = TvNet(C_IN, H, W, max_batch=a.batch)
     net.set_params(init_params(C_IN, seed=0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = train(net, tr, prof, H, W, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    hist = train(net, tr, prof, H, W, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log, param=param)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     te = inputs.couette_instances(a.n_test, seed=2027)
-    res = warm_vs_uniform(net, te, H, W, log=log, tune=tune)
+    res = warm_vs_uniform(net, te, H, W, log=log, tune=tune, param=param)
     res.update({"data_generation_s": t_gen, "training_s": t_train, "n_train": a.n_train,
-                "epochs": a.epochs, "final_loss": hist[-1], "train_steps_mean": float(np.mean(steps))})
+                "epochs": a.epochs, "final_loss": hist[-1], "train_steps_mean": float(np.mean(steps)),
+                "residual": param["residual"], "out_scale": param["scale"].tolist()})
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)
