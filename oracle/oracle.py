@@ -1,4 +1,5 @@
-"""Python view of the FP64 CPU oracle (``tvlbm_oracle.c``).
+"""Python view of the FP64 CPU oracle (``tvlbm_oracle.c``, and
+``tvlbm_fv_oracle.c`` for the finite-volume update).
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
 the CPU-baseline leg of the benchmark.  The product library never imports
@@ -17,7 +18,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "tvlbm_oracle.c")
+_SRCS = [os.path.join(_HERE, "tvlbm_oracle.c"), os.path.join(_HERE, "tvlbm_fv_oracle.c")]
+_HDRS = [os.path.join(_HERE, "tvlbm_oracle.h"), os.path.join(_HERE, "tvlbm_fv_oracle.h")]
 _LIB_DIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_LIB_DIR, "libtvlbm_oracle.so")
 
@@ -73,11 +75,12 @@ class Grid(ctypes.Structure):
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, FP64, no contraction)."""
     os.makedirs(_LIB_DIR, exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS + _HDRS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-            "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+            "-shared", "-std=c11", "-Wall", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -118,6 +121,25 @@ def lib():
         _lib.orc_residual.argtypes = [_dp, _dp, ctypes.c_long, ctypes.c_int]
         _lib.orc_residual.restype = ctypes.c_double
         _lib.orc_threads.restype = ctypes.c_int
+        FG = ctypes.POINTER(FVGrid)
+        _lib.orc_fv_init.argtypes = [L, FG, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]
+        _lib.orc_fv_free.argtypes = [FG]
+        _lib.orc_fv_free.restype = None
+        _lib.orc_fv_impose.argtypes = [L, FG, _dp]
+        _lib.orc_fv_impose.restype = None
+        _lib.orc_fv_set_fields.argtypes = [L, FG, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib.orc_fv_set_fields.restype = None
+        _lib.orc_fv_step.argtypes = [L, FG, _dp, _dp]
+        _lib.orc_fv_step.restype = None
+        _lib.orc_fv_run.argtypes = [L, FG, _dp, ctypes.c_int]
+        _lib.orc_fv_run.restype = None
+        _lib.orc_fv_dual.argtypes = [FG, ctypes.c_int]
+        _lib.orc_fv_dual.restype = ctypes.c_double
+        _lib.orc_fv_totals.argtypes = [L, FG, _dp, _dp]
+        _lib.orc_fv_totals.restype = None
     return _lib
 
 
@@ -248,6 +270,96 @@ class OracleGrid:
         lo, hi = np.zeros(self.nx), np.zeros(self.nx)
         lib().orc_wall_emitted(*self._args(), _p(fstar), _p(lo), _p(hi))
         return lo, hi
+
+
+class FVGrid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int),
+        ("ny", ctypes.c_int),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("collide", ctypes.c_int),
+        ("walls", ctypes.c_int),
+        ("ulo", ctypes.c_double),
+        ("Tlo", ctypes.c_double),
+        ("uhi", ctypes.c_double),
+        ("Thi", ctypes.c_double),
+        ("dy", _dp),
+        ("emit_lo", ctypes.c_double * QMAX),
+        ("emit_hi", ctypes.c_double * QMAX),
+    ]
+
+
+class OracleFVGrid:
+    """Mesh for the finite-volume update (``tvlbm_fv_oracle.h``); f arrays
+    are [q][ny][nx] float64 over the mesh points."""
+
+    def __init__(self, lat: OracleLattice, nx: int, ny: int, dx: float, dt: float, tau: float,
+                 dy=None, collide=True, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0)):
+        self.lat = lat
+        self.nx, self.ny = nx, ny
+        self.g = FVGrid()
+        self._dy = None if dy is None else np.ascontiguousarray(dy, dtype=np.float64)
+        rc = lib().orc_fv_init(ctypes.byref(lat.c), ctypes.byref(self.g), nx, ny, dx,
+                               None if self._dy is None else _p(self._dy), dt, tau, int(collide),
+                               int(walls), wall_lo[0], wall_lo[1], wall_hi[0], wall_hi[1])
+        if rc != 0:
+            lib().orc_fv_free(ctypes.byref(self.g))
+            raise ValueError("invalid finite-volume mesh")
+        self.dual = np.array([lib().orc_fv_dual(ctypes.byref(self.g), j) for j in range(ny)])
+
+    def __del__(self):
+        try:
+            lib().orc_fv_free(ctypes.byref(self.g))
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.lat.q, self.ny, self.nx)
+
+    def _args(self):
+        return ctypes.byref(self.lat.c), ctypes.byref(self.g)
+
+    def set_fields(self, rho, ux, uy, T, noise=None) -> np.ndarray:
+        fld = [np.ascontiguousarray(np.broadcast_to(a, (self.ny, self.nx)), dtype=np.float64)
+               for a in (rho, ux, uy, T)]
+        f = np.zeros(self.shape)
+        nz = None if noise is None else _p(np.ascontiguousarray(noise, dtype=np.float64))
+        lib().orc_fv_set_fields(*self._args(), *[_p(a) for a in fld], nz, _p(f))
+        return f
+
+    def impose(self, f):
+        f = np.array(f, dtype=np.float64, copy=True, order="C")
+        lib().orc_fv_impose(*self._args(), _p(f))
+        return f
+
+    def step(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(self.shape)
+        lib().orc_fv_step(*self._args(), _p(f), _p(out))
+        return out
+
+    def run(self, f, nsteps: int):
+        f = np.array(f, dtype=np.float64, copy=True, order="C")
+        lib().orc_fv_run(*self._args(), _p(f), int(nsteps))
+        return f
+
+    def totals(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(4)
+        lib().orc_fv_totals(*self._args(), _p(f), _p(out))
+        return out
+
+    def fields(self, f):
+        """(rho, ux, uy, T) at every mesh point, [4][ny][nx]."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros((4, self.ny, self.nx))
+        for j in range(self.ny):
+            for i in range(self.nx):
+                out[:, j, i] = self.lat.moments(np.ascontiguousarray(f[:, j, i]))
+        return out
 
 
 def residual(q: np.ndarray, qprev: np.ndarray, K: int) -> float:
