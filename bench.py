@@ -73,6 +73,46 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
     }
 
 
+def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls: bool = True):
+    """The finite-volume update, eq.(FVLB), on a size x size mesh: walls at the
+    first and last rows on the hyperbolic-tangent mesh of Sec. VIII scaled to
+    spacings 0.5 .. ~2.3 (or periodic and uniform), dt = 0.05, tau = 0.2."""
+    import numpy as np
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.tvlbm import FVSolver
+
+    dy = None
+    if walls:
+        y = inputs.tanh_mesh(10.0, size - 1, 2.3)
+        dy = np.diff(y)
+        dy = dy * (0.5 / dy.min())
+    s = FVSolver(size, size, n_gh=n, dtype=dtype, dx=1.0, dt=0.05, tau=0.2, dy=dy, walls=walls,
+                 wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1), device="cuda:0")
+    s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
+    s.step(warmup)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(steps)
+    b.record(s.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    _, tot = s.moments()
+    s.close()
+    q, cells = n * n, size * size
+    esz = 4 if dtype == "f32" else 8
+    bytes_per_step = 2 * esz * q * cells  # algorithmic: read f, write f' once per step
+    return {"mlups": round(cells * steps / (ms / 1e3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 5),
+            "achieved_gbs": round(bytes_per_step / (ms / 1e3 / steps) / 1e9, 1),
+            "frac": round(bytes_per_step / (ms / 1e3 / steps) / 1e9 / HBM_PEAK_GBS, 4),
+            "finite": bool(np.isfinite(tot).all()), "walls": walls, "dtype": dtype,
+            "lattice": f"D2Q{q}"}
+
+
 def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100,
                 solve: bool = True, load_steps: int = 500):
     """Batched steady solves of the thermal-Couette sampler (seed 2026) in one
@@ -266,6 +306,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling measurement")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 lines (1024^2 and 64^2)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
+    ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume legs")
+    ap.add_argument("--fv-only", action="store_true", help="run only the finite-volume legs")
     ap.add_argument("--batched-load-only", action="store_true",
                     help="batched leg: full-load steps only, no steady solves")
     args = ap.parse_args()
@@ -281,6 +323,18 @@ def main():
         return r
 
     v16, v36 = args.variant, args.variant36
+    fv = None
+    if not args.no_fv:
+        fv_steps = max(20, args.steps // 4)
+        fv = {"d2q16_f32_walls": leg("FV D2Q16", run_fv, 4, args.size, fv_steps, 10),
+              "d2q16_f32_periodic": leg("FV D2Q16 periodic", run_fv, 4, args.size, fv_steps, 10,
+                                        "f32", False),
+              "d2q36_f32_walls": leg("FV D2Q36", run_fv, 6, args.size, fv_steps // 2, 5),
+              "d2q16_f64_walls": leg("FV D2Q16 FP64", run_fv, 4, args.size, fv_steps // 2, 5,
+                                     "f64")}
+        if args.fv_only:
+            print(json.dumps({"fv": fv}), flush=True)
+            return
     r16 = leg("D2Q16", run_lattice, 4, args.size, args.steps, args.warmup, v16)
     r36 = None if args.no_d2q36 else leg("D2Q36", run_lattice, 6, args.size, args.steps,
                                          args.warmup, v36)
@@ -329,6 +383,7 @@ def main():
         "c0_64x64_f64": c0,
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
         "batched": bat,
+        "finite_volume": fv,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,80 @@
+/*
+ * tvlbm_fv.h -- C ABI of the finite-volume TVLBM update on one MI355X.
+ *
+ * The paper's own discretisation (Sbragaglia & Sugiyama, arXiv 1004.5059):
+ * explicit Euler in time of df_l/dt = Omega_l - c_l . grad f_l, eq.(FVLB),
+ * on a rectangular mesh, uniform in x (spacing dx) with spacings dy_j in y
+ * (Sec. III), with
+ *   - the second-order 9-point stencils of Sec. III for c . grad f and for
+ *     the collision term Omega_l = -(f_l - feq_l)/tau;
+ *   - optional diffuse-scattering wall points at the first and last mesh
+ *     row: incoming populations (c.n <= 0, n the inward normal) advance
+ *     with the one-sided stencils of Sec. VII, eq.(FVLB2); outgoing ones
+ *     are re-emitted with the flux-weighted wall Maxwellian,
+ *     eq.(IMPOSITION), from the new incoming normal flux;
+ *   - the Hermite equilibrium of Sec. II / Appendix A on the same
+ *     tensor-product Gauss-Hermite sets as include/tvlbm.h (c_l = xi_l).
+ * Periodic in x; periodic in y or walled.
+ *
+ * Conventions as in include/tvlbm.h: return TVLBM_OK or a negative
+ * TVLBM_E* code, TVLBM_F32 / TVLBM_F64, device buffers caller-owned,
+ * populations [q][ny][ld] as deviations from the rest weights internally
+ * (the public outputs are f itself), work on the given stream.
+ */
+#ifndef TVLBM_FV_H
+#define TVLBM_FV_H
+
+#include <stdint.h>
+
+#include "tvlbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tvlbm_fv tvlbm_fv;
+
+typedef struct tvlbm_fv_desc {
+  int32_t n_gh;        /* Gauss-Hermite points per axis: 3, 4 or 6          */
+  int32_t eq_order;    /* 2, 3 or 4 (with n_gh 3, 4, 6)                     */
+  int32_t dtype;       /* TVLBM_F32 | TVLBM_F64                             */
+  int32_t compensated; /* FP32: compensated moment sums (1) or plain (0)    */
+  int32_t nx, ny;      /* mesh points; walls need ny >= 3                   */
+  int64_t ld;          /* row pitch in elements (>= nx), 0 = round up to 64 */
+  double dx;           /* x spacing                                         */
+  double dt;           /* time step                                         */
+  double tau;          /* relaxation time (time units), > 0 if collide      */
+  int32_t collide;     /* 0: no collision term                              */
+  int32_t y_bc;        /* TVLBM_BC_PERIODIC | TVLBM_BC_DIFFUSE_WALLS        */
+  double wall_lo_ux, wall_lo_T; /* wall at the first row: x velocity, T      */
+  double wall_hi_ux, wall_hi_T; /* wall at the last row                      */
+  const double *dy;    /* host: spacing after each mesh row, ny entries     */
+                       /* (periodic; the last closes the period) or ny-1    */
+                       /* (walls); NULL = all dx                            */
+  void *f_a, *f_b;     /* device, q*ny*ld elements of dtype each            */
+  void *omega;         /* device scratch for Omega, q*ny*ld elements        */
+  void *stream;        /* hipStream_t or NULL                               */
+} tvlbm_fv_desc;
+
+/* EINVAL on bad sizes, spacings, dt, tau, pitch or null/shared buffers;
+ * EUNSUPPORTED for other lattices or population blocks of 4 GiB or more. */
+int tvlbm_fv_init(const tvlbm_fv_desc *desc, tvlbm_fv **fv);
+int tvlbm_fv_destroy(tvlbm_fv *fv);
+/* f = feq(rho, u, T) + noise (Sec. II; device [ny][nx] fields of dtype,
+ * noise [q][ny][nx] or NULL), then eq.(IMPOSITION) at the walls */
+int tvlbm_fv_set_fields(tvlbm_fv *fv, const void *rho, const void *ux, const void *uy,
+                        const void *T, const void *noise);
+/* nsteps steps of length dt (asynchronous) */
+int tvlbm_fv_step(tvlbm_fv *fv, int32_t nsteps);
+/* f at every mesh point, device [q][ny][nx] */
+int tvlbm_fv_populations(tvlbm_fv *fv, void *out);
+/* fields (device [ny][nx] each, any may be NULL) and FP64 totals (host,
+ * may be NULL): mass, x/y momentum, energy summed with weights
+ * dx * (dy_{j-1} + dy_j)/2 (half cells at walls).  Synchronises. */
+int tvlbm_fv_moments(tvlbm_fv *fv, void *rho, void *ux, void *uy, void *T, double *totals);
+int tvlbm_fv_step_count(const tvlbm_fv *fv, int64_t *k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVLBM_FV_H */

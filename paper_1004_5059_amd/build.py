@@ -17,7 +17,8 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libtvlbm.so")
 OBJ_DIR = os.path.join(OUT_DIR, "obj")
 
-SOURCES = ["tvlbm_kernels.hip", "tvlbm_api.cpp", "tvlbm_tables.cpp", "tvnet_kernels.hip", "tvnet_api.cpp"]
+SOURCES = ["tvlbm_kernels.hip", "tvlbm_api.cpp", "tvlbm_tables.cpp", "tvlbm_fv.hip", "tvlbm_fv_api.cpp",
+           "tvnet_kernels.hip", "tvnet_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,298 @@
+// tvlbm_fv_api.cpp -- C ABI of include/tvlbm_fv.h: mesh set-up, wall
+// re-emission constants and the two-launch finite-volume step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tvlbm_fv.h"
+#include "tvlbm_core.h"
+#include "tvlbm_fv_launch.h"
+#include "tvlbm_hostlat.h"
+#include "tvlbm_launch.h"
+#include "tvlbm_tables.h"
+
+using namespace tvlbm;
+
+struct tvlbm_fv {
+  tvlbm_fv_desc d{};
+  HostLattice hl;
+  bool f64 = false, comp = true;
+  int64_t ld = 0, plane = 0;
+  hipStream_t st = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;  // buf[cur] holds the state
+  int64_t step = 0;
+  std::vector<double> cyh, volh;  // host copies (double)
+  void* d_cy = nullptr;           // [ny] in dtype
+  double* d_vol = nullptr;        // [ny]
+  double* d_part = nullptr;       // block partials of the totals
+  double* d_tot = nullptr;        // 4 totals
+  int nblocks = 0;
+  FvArgs<float> af{};
+  FvArgs<double> ad{};
+};
+
+namespace {
+
+// Wall re-emission, eq.(IMPOSITION), in deviations: an outgoing population
+// (c.n > 0, n the inward normal) becomes d_l = kap_l + phi_l m with m the
+// incoming normal flux of the deviations, phi_l = feq_l(wall) / Z,
+// Z = sum_{c.n > 0} |c.n| feq(wall), kap_l = C phi_l - w_l and
+// C = sum_{c.n <= 0} |c.n| w (the rest-state part of the incoming flux).
+template <typename R>
+void wall_constants(const HostLattice& H, double uw, double Tw, int top, R* kap, R* phi) {
+  double feq[36];
+  host_feq(H, 1.0, uw, 0.0, Tw, feq);
+  double z = 0.0, cin = 0.0;
+  for (int l = 0; l < H.q; ++l) {
+    const double cn = top ? -H.xi[2 * l + 1] : H.xi[2 * l + 1];
+    if (cn > 0.0) z += cn * feq[l];
+    else cin += -cn * H.w[l];
+  }
+  for (int l = 0; l < QMAX; ++l) { kap[l] = R(0); phi[l] = R(0); }
+  for (int l = 0; l < H.q; ++l) {
+    const double cn = top ? -H.xi[2 * l + 1] : H.xi[2 * l + 1];
+    if (cn > 0.0) {
+      const double p = feq[l] / z;
+      phi[l] = (R)p;
+      kap[l] = (R)(cin * p - H.w[l]);
+    }
+  }
+}
+
+template <typename R>
+void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
+  std::memset(&A, 0, sizeof A);
+  fill_lat(v->hl, A.lat);
+  A.nx = v->d.nx;
+  A.ny = v->d.ny;
+  A.walls = v->d.y_bc == TVLBM_BC_DIFFUSE_WALLS;
+  A.collide = v->d.collide != 0;
+  A.ld = v->ld;
+  A.plane = v->plane;
+  A.dt = (R)v->d.dt;
+  A.inv_tau = v->d.collide ? (R)(1.0 / v->d.tau) : R(0);
+  A.inv_dx = (R)(2.0 / (v->d.dx + v->d.dx));
+  A.cy = (const R*)v->d_cy;
+  A.vol = v->d_vol;
+  if (A.walls) {
+    wall_constants<R>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, A.kap_lo, A.phi_lo);
+    wall_constants<R>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, A.kap_hi, A.phi_hi);
+  }
+}
+
+template <typename R>
+FvArgs<R>& args_of(tvlbm_fv* v);
+template <>
+FvArgs<float>& args_of<float>(tvlbm_fv* v) { return v->af; }
+template <>
+FvArgs<double>& args_of<double>(tvlbm_fv* v) { return v->ad; }
+
+template <typename R>
+int launch(tvlbm_fv* v, int what, const void* src, void* dst, void* fields, double* partials) {
+  FvArgs<R> A = args_of<R>(v);
+  A.src = (const R*)src;
+  A.dst = (R*)dst;
+  A.om = (R*)v->d.omega;
+  return launch_fv(v->hl.n, v->comp, what, A, (R*)fields, partials, v->st) == hipSuccess
+             ? TVLBM_OK
+             : TVLBM_EHIP;
+}
+
+int run(tvlbm_fv* v, int what, const void* src, void* dst, void* fields = nullptr,
+        double* partials = nullptr) {
+  return v->f64 ? launch<double>(v, what, src, dst, fields, partials)
+                : launch<float>(v, what, src, dst, fields, partials);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvlbm_fv_init(const tvlbm_fv_desc* d, tvlbm_fv** out) {
+  if (!d || !out) return TVLBM_EINVAL;
+  *out = nullptr;
+  if (d->dtype != TVLBM_F32 && d->dtype != TVLBM_F64) return TVLBM_EINVAL;
+  const int walls = d->y_bc == TVLBM_BC_DIFFUSE_WALLS;
+  if (d->y_bc != TVLBM_BC_PERIODIC && !walls) return TVLBM_EINVAL;
+  if (d->nx < 2 || d->ny < (walls ? 3 : 2)) return TVLBM_EINVAL;
+  if (!(d->dx > 0.0) || !std::isfinite(d->dx) || !(d->dt > 0.0) || !std::isfinite(d->dt))
+    return TVLBM_EINVAL;
+  if (d->collide && !(d->tau > 0.0)) return TVLBM_EINVAL;
+  if (!d->f_a || !d->f_b || !d->omega || d->f_a == d->f_b || d->omega == d->f_a ||
+      d->omega == d->f_b)
+    return TVLBM_EINVAL;
+  const int ns = walls ? d->ny - 1 : d->ny;
+  std::vector<double> dy(ns, d->dx);
+  if (d->dy)
+    for (int j = 0; j < ns; ++j) {
+      dy[j] = d->dy[j];
+      if (!(dy[j] > 0.0) || !std::isfinite(dy[j])) return TVLBM_EINVAL;
+    }
+  tvlbm_fv* v = new (std::nothrow) tvlbm_fv();
+  if (!v) return TVLBM_ENOMEM;
+  if (!build_lattice(d->n_gh, d->eq_order, 0.9, 0, &v->hl)) { delete v; return TVLBM_EUNSUPPORTED; }
+  v->d = *d;
+  v->d.dy = nullptr;
+  v->f64 = d->dtype == TVLBM_F64;
+  v->comp = v->f64 ? false : d->compensated != 0;
+  v->ld = d->ld ? d->ld : (d->nx + 63) / 64 * 64;
+  if (v->ld < d->nx) { delete v; return TVLBM_EINVAL; }
+  v->plane = (int64_t)d->ny * v->ld;
+  if ((double)v->hl.q * (double)v->plane * (v->f64 ? 8.0 : 4.0) >= 4294967296.0) {
+    delete v;
+    return TVLBM_EUNSUPPORTED;
+  }
+  v->st = (hipStream_t)d->stream;
+  v->buf[0] = d->f_a;
+  v->buf[1] = d->f_b;
+  // y-derivative factors 2 / (dy_{j-1} + dy_j), one-sided 2 / dy at walls,
+  // and the dual-cell weights of the totals
+  const int ny = d->ny;
+  v->cyh.assign(ny, 0.0);
+  v->volh.assign(ny, 0.0);
+  for (int j = 0; j < ny; ++j) {
+    double h;
+    if (!walls) {
+      const double dm = dy[(j - 1 + ny) % ny];
+      v->cyh[j] = 2.0 / (dy[j] + dm);
+      h = 0.5 * (dm + dy[j]);
+    } else if (j == 0) {
+      v->cyh[j] = 2.0 / dy[0];
+      h = 0.5 * dy[0];
+    } else if (j == ny - 1) {
+      v->cyh[j] = 2.0 / dy[ny - 2];
+      h = 0.5 * dy[ny - 2];
+    } else {
+      v->cyh[j] = 2.0 / (dy[j] + dy[j - 1]);
+      h = 0.5 * (dy[j - 1] + dy[j]);
+    }
+    v->volh[j] = d->dx * h;
+  }
+  v->nblocks = (int)(((d->nx + 63) / 64) * ((ny + 3) / 4));
+  const size_t esz = v->f64 ? 8 : 4;
+  bool ok = hipMalloc(&v->d_cy, esz * ny) == hipSuccess &&
+            hipMalloc(&v->d_vol, sizeof(double) * ny) == hipSuccess &&
+            hipMalloc(&v->d_part, sizeof(double) * 4 * v->nblocks) == hipSuccess &&
+            hipMalloc(&v->d_tot, sizeof(double) * 4) == hipSuccess;
+  if (ok) {
+    if (v->f64) {
+      ok = hipMemcpy(v->d_cy, v->cyh.data(), 8 * ny, hipMemcpyHostToDevice) == hipSuccess;
+    } else {
+      std::vector<float> c(v->cyh.begin(), v->cyh.end());
+      ok = hipMemcpy(v->d_cy, c.data(), 4 * ny, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    ok = ok && hipMemcpy(v->d_vol, v->volh.data(), 8 * ny, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) { tvlbm_fv_destroy(v); return TVLBM_ENOMEM; }
+  fill_args(v, v->af);
+  fill_args(v, v->ad);
+  *out = v;
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_destroy(tvlbm_fv* v) {
+  if (!v) return TVLBM_EINVAL;
+  if (v->st) hipStreamSynchronize(v->st);
+  hipFree(v->d_cy);
+  hipFree(v->d_vol);
+  hipFree(v->d_part);
+  hipFree(v->d_tot);
+  delete v;
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_set_fields(tvlbm_fv* v, const void* rho, const void* ux, const void* uy,
+                        const void* T, const void* noise) {
+  if (!v || !rho || !ux || !uy || !T) return TVLBM_EINVAL;
+  // f = feq(fields) + noise as deviations (the lattice step's initialiser;
+  // its post-collision output goes to the Omega scratch and is unused)
+  if (v->f64) {
+    InitArgs<double> A;
+    std::memset(&A, 0, sizeof A);
+    A.lat = v->ad.lat;
+    A.inst.ld = v->ld;
+    A.inst.plane = v->plane;
+    A.inst.nx = v->d.nx;
+    A.inst.ny = v->d.ny;
+    A.rho = (const double*)rho; A.ux = (const double*)ux; A.uy = (const double*)uy;
+    A.T = (const double*)T;
+    A.noise = (const double*)noise;
+    A.f0 = (double*)v->buf[0];
+    A.g0 = (double*)v->d.omega;
+    if (launch_init(v->hl.n, false, A, v->st) != hipSuccess) return TVLBM_EHIP;
+  } else {
+    InitArgs<float> A;
+    std::memset(&A, 0, sizeof A);
+    A.lat = v->af.lat;
+    A.inst.ld = v->ld;
+    A.inst.plane = v->plane;
+    A.inst.nx = v->d.nx;
+    A.inst.ny = v->d.ny;
+    A.rho = (const float*)rho; A.ux = (const float*)ux; A.uy = (const float*)uy;
+    A.T = (const float*)T;
+    A.noise = (const float*)noise;
+    A.f0 = (float*)v->buf[0];
+    A.g0 = (float*)v->d.omega;
+    if (launch_init(v->hl.n, v->comp, A, v->st) != hipSuccess) return TVLBM_EHIP;
+  }
+  v->cur = 0;
+  v->step = 0;
+  return run(v, FV_IMPOSE, nullptr, v->buf[0]);
+}
+
+int tvlbm_fv_step(tvlbm_fv* v, int32_t nsteps) {
+  if (!v || nsteps < 0) return TVLBM_EINVAL;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    int rc = run(v, FV_OMEGA, v->buf[v->cur], nullptr);
+    if (rc) return rc;
+    rc = run(v, FV_UPDATE, v->buf[v->cur], v->buf[v->cur ^ 1]);
+    if (rc) return rc;
+    v->cur ^= 1;
+    ++v->step;
+  }
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_populations(tvlbm_fv* v, void* out) {
+  if (!v || !out) return TVLBM_EINVAL;
+  return run(v, FV_POPS, v->buf[v->cur], nullptr, out);
+}
+
+int tvlbm_fv_moments(tvlbm_fv* v, void* rho, void* ux, void* uy, void* T, double* totals) {
+  if (!v) return TVLBM_EINVAL;
+  const size_t esz = v->f64 ? 8 : 4;
+  const int64_t np = (int64_t)v->d.nx * v->d.ny;
+  void* fld = nullptr;
+  const bool want = rho || ux || uy || T;
+  if (want && hipMallocAsync(&fld, esz * 4 * np, v->st) != hipSuccess) return TVLBM_ENOMEM;
+  int rc = run(v, FV_FIELDS, v->buf[v->cur], nullptr, fld, v->d_part);
+  if (rc == TVLBM_OK && launch_reduce(v->d_part, v->nblocks, 4, v->d_tot, v->st) != hipSuccess)
+    rc = TVLBM_EHIP;
+  void* outs[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4 && rc == TVLBM_OK && want; ++k)
+    if (outs[k] &&
+        hipMemcpyAsync(outs[k], (char*)fld + k * np * esz, np * esz, hipMemcpyDeviceToDevice,
+                       v->st) != hipSuccess)
+      rc = TVLBM_EHIP;
+  double tot[4] = {0, 0, 0, 0};
+  if (rc == TVLBM_OK &&
+      hipMemcpyAsync(tot, v->d_tot, sizeof tot, hipMemcpyDeviceToHost, v->st) != hipSuccess)
+    rc = TVLBM_EHIP;
+  if (fld) hipFreeAsync(fld, v->st);
+  if (hipStreamSynchronize(v->st) != hipSuccess && rc == TVLBM_OK) rc = TVLBM_EHIP;
+  if (rc == TVLBM_OK && totals) std::memcpy(totals, tot, sizeof tot);
+  return rc;
+}
+
+int tvlbm_fv_step_count(const tvlbm_fv* v, int64_t* k) {
+  if (!v || !k) return TVLBM_EINVAL;
+  *k = v->step;
+  return TVLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// tvlbm_fv_launch.h -- parameter block and launchers of the finite-volume
+// TVLBM kernels (tvlbm_fv.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tvlbm_core.h"
+
+namespace tvlbm {
+
+template <typename R>
+struct FvArgs {
+  Lat<R> lat;           // nodes x_a, x_a^2, weights w_l (FP64 copies for totals)
+  int32_t nx, ny;       // mesh points
+  int32_t walls;        // 0 periodic in y, 1 wall points at j = 0 and ny-1
+  int32_t collide;      // 0: Omega = 0
+  int64_t ld, plane;    // row pitch, ny * ld
+  R dt, inv_tau;        // time step, 1/tau
+  R inv_dx;             // 2 / (dx + dx)
+  const R* cy;          // [ny] y-derivative factors: 2/(dy_{j-1} + dy_j), at walls 2/dy
+  const double* vol;    // [ny] dx * dual-cell height (totals)
+  R kap_lo[QMAX], phi_lo[QMAX];  // re-emission at the bottom wall: d = kap + phi m
+  R kap_hi[QMAX], phi_hi[QMAX];  // and at the top wall
+  const R* src;         // d at t
+  R* dst;               // d at t + dt
+  R* om;                // Omega at t
+};
+
+enum FvKernel { FV_OMEGA = 0, FV_UPDATE = 1, FV_FIELDS = 2, FV_IMPOSE = 3, FV_POPS = 4 };
+
+// FV_FIELDS: fields [4][ny][nx] or null, partials [blocks][4];
+// FV_POPS: fields is the [q][ny][nx] output; FV_IMPOSE acts on A.dst.
+hipError_t launch_fv(int n, bool comp, int what, const FvArgs<float>& A, float* fields,
+                     double* partials, hipStream_t st);
+hipError_t launch_fv(int n, bool comp, int what, const FvArgs<double>& A, double* fields,
+                     double* partials, hipStream_t st);
+
+}  // namespace tvlbm

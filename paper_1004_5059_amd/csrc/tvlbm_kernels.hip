@@ -32,42 +32,6 @@ __host__ __device__ constexpr int node_sign(int a) {
   return (2 * a + 1 < N) ? -1 : ((2 * a + 1 > N) ? 1 : 0);
 }
 
-// Buffer addressing: one resource per instance block (base and size in
-// SGPRs); the lane offset (row, column) is a VGPR and the population plane
-// offset l * plane is a wave-uniform SGPR offset, so no per-load address
-// arithmetic is spent on the vector ALUs.  Accesses beyond the block return
-// zero instead of faulting.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename R>
-__device__ __forceinline__ R bld(rsrc_t r, uint32_t v, uint32_t s);
-template <>
-__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t v, uint32_t s) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v * 4u, s * 4u, 0));
-}
-template <>
-__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t v, uint32_t s) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8u, s * 8u, 0));
-}
-__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, float x) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, v * 4u, s * 4u, 0);
-}
-__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, double x) {
-  using v2i = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, x), r, v * 8u, s * 8u, 0);
-}
-// column pairs: offsets count pairs (8 bytes)
-template <>
-__device__ __forceinline__ f32x2 bld<f32x2>(rsrc_t r, uint32_t v, uint32_t s) {
-  return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8u, s * 8u, 0));
-}
-__device__ __forceinline__ void bst(rsrc_t r, uint32_t v, uint32_t s, f32x2 x) {
-  using v2i = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, x), r, v * 8u, s * 8u, 0);
-}
-
 // Lane offsets of one row: centre, left and right neighbour (periodic in x).
 struct RowOff {
   uint32_t c, m, p;

@@ -93,6 +93,32 @@ class tvlbm_batch_tuning(ctypes.Structure):
                 ("tail_width", ctypes.c_int32), ("tail_rows", ctypes.c_int32)]
 
 
+class tvlbm_fv_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_gh", ctypes.c_int32),
+        ("eq_order", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("compensated", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("ld", ctypes.c_int64),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("collide", ctypes.c_int32),
+        ("y_bc", ctypes.c_int32),
+        ("wall_lo_ux", ctypes.c_double),
+        ("wall_lo_T", ctypes.c_double),
+        ("wall_hi_ux", ctypes.c_double),
+        ("wall_hi_T", ctypes.c_double),
+        ("dy", ctypes.POINTER(ctypes.c_double)),
+        ("f_a", ctypes.c_void_p),
+        ("f_b", ctypes.c_void_p),
+        ("omega", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 class TvlbmError(RuntimeError):
     def __init__(self, code: int, detail: str = ""):
         self.code = code
@@ -143,6 +169,13 @@ def lib():
         "tvlbm_batch_fields": [_vp, _vp],
         "tvlbm_batch_set_shape": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
         "tvlbm_batch_set_tuning": [_vp, ctypes.c_void_p],
+        "tvlbm_fv_init": [ctypes.c_void_p, ctypes.POINTER(_vp)],
+        "tvlbm_fv_destroy": [_vp],
+        "tvlbm_fv_set_fields": [_vp, _vp, _vp, _vp, _vp, _vp],
+        "tvlbm_fv_step": [_vp, ctypes.c_int32],
+        "tvlbm_fv_populations": [_vp, _vp],
+        "tvlbm_fv_moments": [_vp, _vp, _vp, _vp, _vp, _dp],
+        "tvlbm_fv_step_count": [_vp, _i64p],
         "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
@@ -682,3 +715,120 @@ class TvNet:
     def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
         self.t += 1
         tvnet_adam_step(self.h, lr, b1, b2, eps, self.t)
+
+
+# ------------------------------------------------------ finite volume ---
+def tvlbm_fv_init(desc: tvlbm_fv_desc):
+    h = _vp()
+    _check(lib().tvlbm_fv_init(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def tvlbm_fv_destroy(h):
+    _check(lib().tvlbm_fv_destroy(h))
+
+
+def tvlbm_fv_set_fields(h, rho, ux, uy, T, noise=None):
+    _check(lib().tvlbm_fv_set_fields(h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(noise)))
+
+
+def tvlbm_fv_step(h, nsteps: int):
+    _check(lib().tvlbm_fv_step(h, int(nsteps)))
+
+
+def tvlbm_fv_populations(h, out):
+    _check(lib().tvlbm_fv_populations(h, _ptr(out)))
+
+
+def tvlbm_fv_moments(h, rho=None, ux=None, uy=None, T=None):
+    tot = (ctypes.c_double * 4)()
+    _check(lib().tvlbm_fv_moments(h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), tot))
+    return np.array(tot[:])
+
+
+def tvlbm_fv_step_count(h) -> int:
+    k = ctypes.c_int64()
+    _check(lib().tvlbm_fv_step_count(h, ctypes.byref(k)))
+    return k.value
+
+
+class FVSolver:
+    """The paper's finite-volume update, eq.(FVLB), on a mesh uniform in x
+    (spacing dx) with spacings dy in y; periodic or with diffuse-scattering
+    wall points (eq.(FVLB2), eq.(IMPOSITION)).  dy: ny spacings (periodic,
+    the last closes the period) or ny-1 (walls); None = all dx."""
+
+    def __init__(self, nx: int, ny: int, n_gh: int = 4, dtype: str = "f32", dx: float = 1.0,
+                 dt: float = 0.1, tau: float = 0.8, dy=None, walls: bool = False,
+                 wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0), collide: bool = True,
+                 compensated: bool = True, device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device or "cuda:0")
+        self.nx, self.ny, self.n, self.q = nx, ny, n_gh, n_gh * n_gh
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        self.ld = ((nx + 63) // 64) * 64
+        n_el = self.q * ny * self.ld
+        self.f_a = torch.zeros(n_el, dtype=self.tdtype, device=self.device)
+        self.f_b = torch.zeros(n_el, dtype=self.tdtype, device=self.device)
+        self.om = torch.zeros(n_el, dtype=self.tdtype, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        d = tvlbm_fv_desc()
+        d.n_gh, d.eq_order = n_gh, LATTICE_ORDER[n_gh]
+        d.dtype = TVLBM_F32 if dtype == "f32" else TVLBM_F64
+        d.compensated = int(compensated)
+        d.nx, d.ny, d.ld = nx, ny, self.ld
+        d.dx, d.dt, d.tau = dx, dt, tau
+        d.collide = int(collide)
+        d.y_bc = TVLBM_BC_DIFFUSE_WALLS if walls else TVLBM_BC_PERIODIC
+        d.wall_lo_ux, d.wall_lo_T = wall_lo
+        d.wall_hi_ux, d.wall_hi_T = wall_hi
+        self._dy = None
+        if dy is not None:
+            self._dy = (ctypes.c_double * len(dy))(*[float(v) for v in dy])
+            d.dy = ctypes.cast(self._dy, ctypes.POINTER(ctypes.c_double))
+        d.f_a, d.f_b, d.omega = self.f_a.data_ptr(), self.f_b.data_ptr(), self.om.data_ptr()
+        d.stream = self.stream.cuda_stream
+        self.h = tvlbm_fv_init(d)
+
+    def close(self):
+        if getattr(self, "h", None):
+            tvlbm_fv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, shape):
+        t = self.torch.as_tensor(np.ascontiguousarray(np.broadcast_to(a, shape)), dtype=self.tdtype)
+        return t.to(self.device).contiguous()
+
+    def set_fields(self, rho, ux, uy, T, noise=None):
+        shp = (self.ny, self.nx)
+        fl = [self._dev(a, shp) for a in (rho, ux, uy, T)]
+        nz = None if noise is None else self._dev(noise, (self.q, self.ny, self.nx))
+        tvlbm_fv_set_fields(self.h, *fl, nz)
+        self.stream.synchronize()
+
+    def step(self, n: int = 1):
+        tvlbm_fv_step(self.h, n)
+
+    def populations(self):
+        out = self.torch.empty((self.q, self.ny, self.nx), dtype=self.tdtype, device=self.device)
+        tvlbm_fv_populations(self.h, out)
+        self.stream.synchronize()
+        return out
+
+    def moments(self):
+        outs = [self.torch.empty((self.ny, self.nx), dtype=self.tdtype, device=self.device)
+                for _ in range(4)]
+        tot = tvlbm_fv_moments(self.h, *outs)
+        return self.torch.stack(outs), tot
+
+    @property
+    def step_count(self) -> int:
+        return tvlbm_fv_step_count(self.h)

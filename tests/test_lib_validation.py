@@ -163,3 +163,39 @@ def test_host_lattice_tables_match_the_oracle(n, order, cfl, norm):
 def test_lattice_table_rejects_unsupported():
     assert _code(T.tvlbm_lattice_table, 5, 3) == T.TVLBM_EUNSUPPORTED
     assert _code(T.tvlbm_lattice_table, 4, 3, 0.0) == T.TVLBM_EUNSUPPORTED
+
+
+def _fv_desc(**kw):
+    d = T.tvlbm_fv_desc()
+    d.n_gh, d.eq_order, d.dtype, d.compensated = 4, 3, T.TVLBM_F32, 1
+    d.nx, d.ny, d.ld = 32, 16, 0
+    d.dx, d.dt, d.tau = 1.0, 0.05, 0.2
+    d.collide, d.y_bc = 1, T.TVLBM_BC_PERIODIC
+    d.wall_lo_T = d.wall_hi_T = 1.0
+    d.f_a, d.f_b, d.omega = FA, FB, 0x300000
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dt=0.0), dict(dt=-1.0), dict(dx=0.0), dict(tau=0.0), dict(nx=1), dict(ny=1),
+    dict(y_bc=T.TVLBM_BC_DIFFUSE_WALLS, ny=2), dict(dtype=5), dict(y_bc=7),
+    dict(omega=FA), dict(f_b=FA), dict(omega=None), dict(ld=16), dict(dt=float("nan")),
+])
+def test_fv_init_rejects_invalid_descriptors(kw):
+    assert _code(T.tvlbm_fv_init, _fv_desc(**kw)) == T.TVLBM_EINVAL
+
+
+def test_fv_init_rejects_bad_spacings_and_lattices():
+    dy = (ctypes.c_double * 16)(*([1.0] * 15 + [-0.5]))
+    d = _fv_desc(dy=ctypes.cast(dy, ctypes.POINTER(ctypes.c_double)))
+    assert _code(T.tvlbm_fv_init, d) == T.TVLBM_EINVAL
+    assert _code(T.tvlbm_fv_init, _fv_desc(n_gh=5)) == T.TVLBM_EUNSUPPORTED
+
+
+def test_fv_descriptor_layout_matches_header():
+    d = T.tvlbm_fv_desc
+    assert d.ld.offset == 24 and d.dx.offset == 32 and d.collide.offset == 56
+    assert d.wall_lo_ux.offset == 64 and d.dy.offset == 96 and d.omega.offset == 120
+    assert ctypes.sizeof(d) == 136
