@@ -74,6 +74,24 @@ int tvlbm_fv_populations(tvlbm_fv *fv, void *out);
 int tvlbm_fv_moments(tvlbm_fv *fv, void *rho, void *ux, void *uy, void *T, double *totals);
 int tvlbm_fv_step_count(const tvlbm_fv *fv, int64_t *k);
 
+/* How a step runs on the GPU.  fused = 1 (the default): one pass that reads
+ * the populations once and writes them once; each wavefront marches down
+ * seg_rows rows of a 62-column strip, the 9-point stencils of Sec. III and
+ * Sec. VII evaluated in their separable (1-D x 1-D) form.  fused = 0: two
+ * passes, Omega of every point into the omega scratch array, then the
+ * stencil update.  Both compute the same update; they differ by rounding
+ * only (the fused pass sums the stencil terms in another order).
+ * seg_rows: 1 .. 65536 rows per wavefront (0 keeps the current value,
+ * default 6); prefetch: 1 loads row r+1 while row r is processed (default 0).
+ * EINVAL on a null handle or argument, or values out of range. */
+typedef struct tvlbm_fv_schedule {
+  int32_t fused;
+  int32_t seg_rows;
+  int32_t prefetch;
+} tvlbm_fv_schedule;
+int tvlbm_fv_set_schedule(tvlbm_fv *fv, const tvlbm_fv_schedule *s);
+int tvlbm_fv_get_schedule(const tvlbm_fv *fv, tvlbm_fv_schedule *s);
+
 #ifdef __cplusplus
 }
 #endif

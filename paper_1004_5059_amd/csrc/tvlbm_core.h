@@ -10,6 +10,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace tvlbm {
@@ -161,23 +163,30 @@ __device__ __forceinline__ f32x2 fmaR(f32x2 a, f32x2 b, f32x2 c) {
 }
 
 // ------------------------------------------------------ compensation -----
-// Kahan's compensated summation: (s, c) accumulates x with the rounding
-// error of every addition carried in c (the value is s - c).
+// Compensated FP32 sums are accumulated in FP64: a product of an FP32 node
+// and an FP32 deviation is exact there, and a sum of at most 36 such terms
+// keeps ~53 - 5 bits, so the moments are rounded to FP32 once, at the end.
+// On this chip FP64 vector operations issue at the FP32 rate, which makes
+// this cheaper than Kahan summation in FP32 (one conversion per value
+// instead of four operations per addition).
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename R>
-__device__ __forceinline__ void kahan_add(R& s, R& c, R x) {
-  const R y = x - c;
-  const R t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-// Compensated dot-product term: the product a*b is split exactly into
-// p + e (TwoProduct with a fused multiply-add); p is added with Kahan's
-// scheme and e into a separate low-order accumulator.
+struct WideT { using T = double; };
+template <>
+struct WideT<f32x2> { using T = f64x2; };
+__device__ __forceinline__ double widen(float x) { return (double)x; }
+__device__ __forceinline__ double widen(double x) { return x; }
+__device__ __forceinline__ f64x2 widen(f32x2 x) { return __builtin_convertvector(x, f64x2); }
 template <typename R>
-__device__ __forceinline__ void kahan_dot(R& s, R& c, R& lo, R a, R b) {
-  const R p = a * b;
-  lo += fmaR(a, b, -p);
-  kahan_add(s, c, p);
+__device__ __forceinline__ R narrow(typename WideT<R>::T x);
+template <>
+__device__ __forceinline__ float narrow<float>(double x) { return (float)x; }
+template <>
+__device__ __forceinline__ double narrow<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ f32x2 narrow<f32x2>(f64x2 x) { return __builtin_convertvector(x, f32x2); }
+__device__ __forceinline__ f64x2 fmaR(f64x2 a, f64x2 b, f64x2 c) {
+  return __builtin_elementwise_fma(a, b, c);
 }
 
 // ---------------------------------------------------------------- moments --
@@ -187,94 +196,60 @@ __device__ __forceinline__ void kahan_dot(R& s, R& c, R& lo, R a, R b) {
 // from row sums R_a = sum_b d_ab and column sums C_b = sum_a d_ab:
 //   drho = sum_a R_a, jx = sum_a x_a R_a, jy = sum_b x_b C_b,
 //   ed = sum_a x_a^2 R_a + sum_b x_b^2 C_b.
-// COMP: every sum is compensated -- Kahan summation for the row and column
-// sums and for drho, and compensated dot products (exact product split plus
-// Kahan summation) for j and ed, with the low-order parts of the row and
-// column sums carried into the dot products.
+// COMP: the same sums accumulated in FP64 (see above) and rounded once.
+template <typename W, typename R>
+__device__ __forceinline__ W as_w(R x) {
+  if constexpr (std::is_same_v<W, R>) return x;
+  else return widen(x);
+}
+
+template <typename W, typename R, int N>
+__device__ __forceinline__ void tensor_moments(const Lat<R>& L, const W (&v)[N * N], W& r,
+                                               W& x, W& y, W& e) {
+  W ra[N], cb[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) cb[b] = v[b];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    W s = v[a * N];
+#pragma unroll
+    for (int b = 1; b < N; ++b) s += v[a * N + b];
+    ra[a] = s;
+    if (a > 0) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) cb[b] += v[a * N + b];
+    }
+  }
+  r = ra[0];
+  x = as_w<W>(L.x[0]) * ra[0];
+  y = as_w<W>(L.x[0]) * cb[0];
+  e = as_w<W>(L.x2[0]) * ra[0] + as_w<W>(L.x2[0]) * cb[0];
+#pragma unroll
+  for (int a = 1; a < N; ++a) {
+    r += ra[a];
+    x = fmaR(as_w<W>(L.x[a]), ra[a], x);
+    y = fmaR(as_w<W>(L.x[a]), cb[a], y);
+    e = fmaR(as_w<W>(L.x2[a]), ra[a], e);
+    e = fmaR(as_w<W>(L.x2[a]), cb[a], e);
+  }
+}
+
 template <typename R, int N, bool COMP>
 __device__ __forceinline__ void cell_moments(const Lat<R>& L, const R (&d)[N * N], R& drho,
                                              R& jx, R& jy, R& ed) {
   if constexpr (!COMP) {
-    R ra[N], cb[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) cb[b] = d[b];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      R s = d[a * N];
-#pragma unroll
-      for (int b = 1; b < N; ++b) s += d[a * N + b];
-      ra[a] = s;
-      if (a > 0) {
-#pragma unroll
-        for (int b = 0; b < N; ++b) cb[b] += d[a * N + b];
-      }
-    }
-    R r = ra[0], x = L.x[0] * ra[0], y = L.x[0] * cb[0];
-    R e = L.x2[0] * ra[0] + L.x2[0] * cb[0];
-#pragma unroll
-    for (int a = 1; a < N; ++a) {
-      r += ra[a];
-      x = fmaR(L.x[a], ra[a], x);
-      y = fmaR(L.x[a], cb[a], y);
-      e = fmaR(L.x2[a], ra[a], e);
-      e = fmaR(L.x2[a], cb[a], e);
-    }
-    drho = r; jx = x; jy = y; ed = e;
+    tensor_moments<R, R, N>(L, d, drho, jx, jy, ed);
   } else {
-    // row sums (hi, -lo) and column sums
-    R rh[N], rc[N], ch[N], cc[N];
+    using W = typename WideT<R>::T;
+    W v[N * N];
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      R s = d[a * N], c = R(0);
-#pragma unroll
-      for (int b = 1; b < N; ++b) kahan_add(s, c, d[a * N + b]);
-      rh[a] = s; rc[a] = c;
-    }
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      R s = d[b], c = R(0);
-#pragma unroll
-      for (int a = 1; a < N; ++a) kahan_add(s, c, d[a * N + b]);
-      ch[b] = s; cc[b] = c;
-    }
-    {  // drho = sum_a (rh_a - rc_a)
-      R s = rh[0], c = R(0), lo = -rc[0];
-#pragma unroll
-      for (int a = 1; a < N; ++a) {
-        kahan_add(s, c, rh[a]);
-        lo -= rc[a];
-      }
-      drho = s + (lo - c);
-    }
-    {  // jx = sum_a x_a (rh_a - rc_a)
-      R s = R(0), c = R(0), lo = R(0);
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        kahan_dot(s, c, lo, L.x[a], rh[a]);
-        lo = fmaR(-L.x[a], rc[a], lo);
-      }
-      jx = s + (lo - c);
-    }
-    {  // jy = sum_b x_b (ch_b - cc_b)
-      R s = R(0), c = R(0), lo = R(0);
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        kahan_dot(s, c, lo, L.x[b], ch[b]);
-        lo = fmaR(-L.x[b], cc[b], lo);
-      }
-      jy = s + (lo - c);
-    }
-    {  // ed = sum_a x_a^2 (rh_a - rc_a) + sum_b x_b^2 (ch_b - cc_b)
-      R s = R(0), c = R(0), lo = R(0);
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        kahan_dot(s, c, lo, L.x2[a], rh[a]);
-        lo = fmaR(-L.x2[a], rc[a], lo);
-        kahan_dot(s, c, lo, L.x2[a], ch[a]);
-        lo = fmaR(-L.x2[a], cc[a], lo);
-      }
-      ed = s + (lo - c);
-    }
+    for (int l = 0; l < N * N; ++l) v[l] = widen(d[l]);
+    W r, x, y, e;
+    tensor_moments<W, R, N>(L, v, r, x, y, e);
+    drho = narrow<R>(r);
+    jx = narrow<R>(x);
+    jy = narrow<R>(y);
+    ed = narrow<R>(e);
   }
 }
 

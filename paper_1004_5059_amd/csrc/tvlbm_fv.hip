@@ -5,13 +5,17 @@
 // eq.(IMPOSITION)).  Populations are stored as deviations d = f - w, SoA
 // [q][ny][ld], one thread per mesh point, 64 x 4 points per workgroup.
 //
-// A step is two launches:
-//   k_fv_omega: Omega_l = -(f_l - feq_l)/tau at every point (compensated
-//     moments and the per-node equilibrium of the fused lattice step);
-//   k_fv_update: d' = d + dt (Omega-bar - c . grad d), the stencils reading
-//     d and Omega at the 3 x 3 neighbourhood through the caches; at wall
-//     points the incoming populations use the one-sided stencils and the
-//     outgoing ones are re-emitted from the new incoming normal flux.
+// Two schedules of one step:
+//   k_fv_march (fused, one pass): every wavefront marches down one row
+//     segment of a 62-column strip (lanes 0 and 63 are halo columns),
+//     reading d once and writing d' once; see the kernel for the separable
+//     form of the stencils that makes this possible;
+//   k_fv_omega then k_fv_update (two passes): Omega_l = -(f_l - feq_l)/tau
+//     at every point into a scratch array, then d' = d + dt (Omega-bar -
+//     c . grad d) with the 3 x 3 stencils reading d and Omega through the
+//     caches.
+// At wall points the incoming populations use the one-sided stencils and
+// the outgoing ones are re-emitted from the new incoming normal flux.
 #include "tvlbm_core.h"
 #include "tvlbm_fv_launch.h"
 
@@ -246,6 +250,281 @@ __global__ __launch_bounds__(256) void k_fv_fields(const FvArgs<R> A, R* fields,
   }
 }
 
+
+// ------------------------------------------------------- fused march ---
+// The stencils of Sec. III are tensor products of 1-D three-point stencils:
+// with S = [1/8, 3/4, 1/8] and the central difference D = [-1, 0, 1],
+//   Omega-bar = S_x S_y Omega,
+//   d/dx f    = S_y D_x f / (2 dx),
+//   d/dy f    = D_y S_x f * cy_j / 2,   cy_j = 2 / (dy_{j-1} + dy_j),
+// and the wall stencils of eq.(FVLB2) are the same with S_y replaced by
+// [3/4, 1/4] (wall row, row into the fluid) and D_y by the one-sided
+// difference.  So one row r needs, per population, the row quantities
+//   a = S_x d,  e = dt S_x Omega - dt c_x D_x d / (2 dx)
+// and the update of row j is
+//   d'_j = d_j + 3/4 e_j + 1/8 (e_{j-1} + e_{j+1}) - h_j (a_{j+1} - a_{j-1}),
+//   h_j = dt c_y cy_j / 2,
+// which a wavefront marching down y accumulates with two partial sums per
+// population: P (row j, waiting for row j+1) and pre (row j+1, from row j).
+// The x neighbours come from the adjacent lanes (DPP wave shifts).
+
+// Value held by lane k-1 (FROM_PREV, wave_shr:1) or k+1 (FROM_NEXT,
+// wave_shl:1) of the wavefront; the end lanes receive 0 (halo lanes).
+constexpr int DPP_FROM_PREV = 0x138;
+constexpr int DPP_FROM_NEXT = 0x130;
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void load_row(rsrc_t s, uint32_t c, int64_t plane, R* d) {
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) d[l] = bld<R>(s, c, (uint32_t)(l * plane));
+}
+
+// eq.(IMPOSITION) at a wall point of the new state (tab: kap then phi of
+// that wall, in device memory so that the constants are loaded only here).
+template <typename R, int N>
+__device__ __forceinline__ void impose(const Lat<R>& L, const R* __restrict__ tab, bool top, R* o) {
+  R m = R(0);
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) {
+    const R cn = top ? -L.x[l % N] : L.x[l % N];
+    if (cn <= R(0)) m = fmaR(-cn, o[l], m);
+  }
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) {
+    const R cn = top ? -L.x[l % N] : L.x[l % N];
+    if (cn > R(0)) o[l] = fmaR(tab[QMAX + l], m, tab[l]);
+  }
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void store_row(rsrc_t dst, uint32_t c, int64_t plane, const R* o) {
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) bst(dst, c, (uint32_t)(l * plane), o[l]);
+}
+
+// W = tau Omega of one row (zero without collisions).
+template <typename R, int N, int ORD, bool COMP>
+__device__ __forceinline__ void row_omega(const Lat<R>& L, bool collide, const R (&d)[N * N],
+                                          R (&w)[N * N]) {
+  if (!collide) {
+#pragma unroll
+    for (int l = 0; l < N * N; ++l) w[l] = R(0);
+    return;
+  }
+  R drho, jx, jy, ed;
+  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<R> F = fields_from(drho, jx, jy, ed);
+  EqNodes<R, N> E;
+  eq_nodes<R, N, ORD>(L, F, E);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    R Fa, Ka, Na;
+    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      w[l] = fmaR(L.w[l], eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na), -d[l]);
+    }
+  }
+}
+
+// Per-wavefront constants of the march.
+template <typename R>
+struct MarchC {
+  rsrc_t s, dst;
+  uint32_t ld, col;
+  int ny, y0, y1, rs, re;
+  bool walls, out_lane;
+  R c1, c2, hx8, hh8;
+  __device__ int wrap(int r) const { return r < 0 ? r + ny : (r >= ny ? r - ny : r); }
+  __device__ uint32_t cell(int r) const { return (uint32_t)wrap(r) * ld + col; }
+};
+
+// Scaled row quantities of population l: a8 = 8 a, e = E (= e / 8).
+template <typename R, int N>
+__device__ __forceinline__ void row_quant(const MarchC<R>& C, R hxa, R d, R w, R& a8, R& e) {
+  const R dm = lane_shift<DPP_FROM_PREV>(d), dp = lane_shift<DPP_FROM_NEXT>(d);
+  const R wm = lane_shift<DPP_FROM_PREV>(w), wp = lane_shift<DPP_FROM_NEXT>(w);
+  a8 = fmaR(R(6), d, dm + dp);
+  e = fmaR(C.c1, wm + wp, fmaR(C.c2, w, -(hxa * (dp - dm))));
+}
+
+// An interior row r between interior rows: finish row r-1 (store), carry
+// row r in P, start row r+1 in pre.
+template <typename R, int N>
+__device__ __forceinline__ void row_steady(const FvArgs<R>& A, const MarchC<R>& C, int r,
+                                           const R (&d)[N * N], const R (&w)[N * N],
+                                           R (&P)[N * N], R (&pre)[N * N]) {
+  const Lat<R>& L = A.lat;
+  const R hp = C.hh8 * A.cy[C.wrap(r - 1)], hn = C.hh8 * A.cy[C.wrap(r + 1)];
+  R hpb[N], hnb[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) { hpb[b] = hp * L.x[b]; hnb[b] = hn * L.x[b]; }
+  const uint32_t cprev = C.cell(r - 1);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const R hxa = C.hx8 * L.x[a];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      R a8, e;
+      row_quant<R, N>(C, hxa, d[l], w[l], a8, e);
+      const R v = fmaR(-hpb[b], a8, P[l] + e);
+      if (C.out_lane) bst(C.dst, cprev, (uint32_t)(l * A.plane), v);
+      P[l] = fmaR(R(6), e, d[l]) + pre[l];
+      pre[l] = fmaR(hnb[b], a8, e);
+    }
+  }
+}
+
+// Any row (segment ends, wall rows): E-weights 1 in the interior and 2 (1/4
+// unscaled) towards a wall row; a wall row's own a-term is +h a at the
+// bottom and -h a at the top (one-sided difference); wall rows are
+// re-emitted, eq.(IMPOSITION), before they are stored.
+template <typename R, int N>
+__device__ __forceinline__ void row_general(const FvArgs<R>& A, const MarchC<R>& C, int r,
+                                            const R (&d)[N * N], const R (&w)[N * N],
+                                            R (&P)[N * N], R (&pre)[N * N]) {
+  const Lat<R>& L = A.lat;
+  const int ny = C.ny;
+  const bool prev_out = r - 1 >= C.y0 && r - 1 < C.y1 && !(C.walls && r - 1 == ny - 1);
+  const bool prev_lo = C.walls && r - 1 == 0;
+  const bool cur_out = r >= C.y0 && r < C.y1;
+  const bool cur_lo = C.walls && r == 0, cur_hi = C.walls && r == ny - 1;
+  const bool next_hi = C.walls && r + 1 == ny - 1;
+  const R hp = C.hh8 * A.cy[C.wrap(r - 1)], hn = C.hh8 * A.cy[C.wrap(r + 1)];
+  const R hc = C.hh8 * A.cy[C.wrap(r)];
+  const R bprev = prev_lo ? R(2) : R(1), bnext = next_hi ? R(2) : R(1);
+  const R kc = cur_lo ? hc : (cur_hi ? -hc : R(0));
+  R o[N * N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const R hxa = C.hx8 * L.x[a];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      R a8, e;
+      row_quant<R, N>(C, hxa, d[l], w[l], a8, e);
+      o[l] = fmaR(-(hp * L.x[b]), a8, fmaR(bprev, e, P[l]));          // row r-1
+      P[l] = fmaR(kc * L.x[b], a8, fmaR(R(6), e, d[l]) + pre[l]);     // row r
+      pre[l] = fmaR(hn * L.x[b], a8, bnext * e);                      // row r+1
+    }
+  }
+  if (prev_out) {
+    if (prev_lo) impose<R, N>(L, A.wtab, false, o);
+    if (C.out_lane) store_row<R, N>(C.dst, C.cell(r - 1), A.plane, o);
+  }
+  if (cur_out && cur_hi) {
+    impose<R, N>(L, A.wtab + 2 * QMAX, true, P);
+    if (C.out_lane) store_row<R, N>(C.dst, C.cell(r), A.plane, P);
+  }
+}
+
+template <typename R, int N, int ORD, bool COMP, bool PF>
+__global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
+  constexpr int Q = N * N;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // workgroups go round-robin to the 8 XCDs: give each XCD a contiguous
+  // band of tiles (gridDim.x is a multiple of 8)
+  const int nb = gridDim.x;
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int strip = t % A.strips;
+  const int seg = (t / A.strips) * 4 + wave;
+  if (seg >= A.segs) return;  // whole wavefront
+  const Lat<R>& L = A.lat;
+  const int nx = A.nx, ny = A.ny;
+  const uint32_t bytes = (uint32_t)(Q * A.plane * (int64_t)sizeof(R));
+  MarchC<R> C;
+  C.s = make_rsrc(A.src, bytes);
+  C.dst = make_rsrc(A.dst, bytes);
+  C.ld = (uint32_t)A.ld;
+  C.ny = ny;
+  C.walls = A.walls != 0;
+  C.y0 = seg * A.seg_rows;
+  C.y1 = min(C.y0 + A.seg_rows, ny);
+  const int x0 = strip * 62;
+  C.col = (uint32_t)((x0 - 1 + lane + nx) % nx);
+  C.out_lane = lane >= 1 && lane <= 62 && x0 - 1 + lane < nx;
+  // Scaled row quantities: a8 = 8 a = (d_{i-1} + d_{i+1}) + 6 d and
+  // E = e / 8 = c1 (W_{i-1} + W_{i+1}) + c2 W - hx8_a (d_{i+1} - d_{i-1}),
+  // W = w_l feq-deviation - d = tau Omega, c1 = dt / (64 tau),
+  // c2 = 3 dt / (32 tau), hx8_a = dt c_x / (16 dx); then
+  //   d'_j = d_j + 6 E_j + E_{j-1} + E_{j+1} - (h_j / 8)(a8_{j+1} - a8_{j-1}).
+  C.c1 = A.dt * A.inv_tau * R(1.0 / 64.0);
+  C.c2 = A.dt * A.inv_tau * R(3.0 / 32.0);
+  C.hx8 = A.dt * A.inv_dx * R(1.0 / 16.0);
+  C.hh8 = A.dt * R(1.0 / 16.0);  // h_j / (8 c_y) = dt cy_j / 16
+  C.rs = C.walls ? max(C.y0 - 1, 0) : C.y0 - 1;
+  C.re = C.walls ? min(C.y1, ny - 1) : C.y1;
+  // rows s0..s1 are interior rows between interior rows of this segment
+  int s0 = C.y0 + 1, s1 = min(C.re - 1, C.y1 - 1);
+  if (C.walls) { s0 = max(s0, 2); s1 = min(s1, ny - 3); }
+  const bool steady = s0 <= s1;
+
+  R P[Q], pre[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) { P[l] = R(0); pre[l] = R(0); }
+  const int g_end = steady ? s0 : C.re + 1;
+  for (int r = C.rs; r < g_end; ++r) {
+    R d[Q], w[Q];
+    load_row<R, N>(C.s, C.cell(r), A.plane, d);
+    row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+    row_general<R, N>(A, C, r, d, w, P, pre);
+  }
+  if (!steady) return;
+  if constexpr (PF) {
+    // two row buffers in turn: row r+1 loads while row r is processed
+    R ba[Q], bb[Q];
+    load_row<R, N>(C.s, C.cell(s0), A.plane, ba);
+    int r = s0;
+    for (; r + 1 <= s1; r += 2) {
+      load_row<R, N>(C.s, C.cell(r + 1), A.plane, bb);
+      {
+        R w[Q];
+        row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
+        row_steady<R, N>(A, C, r, ba, w, P, pre);
+      }
+      if (r + 2 <= s1) load_row<R, N>(C.s, C.cell(r + 2), A.plane, ba);
+      {
+        R w[Q];
+        row_omega<R, N, ORD, COMP>(L, A.collide, bb, w);
+        row_steady<R, N>(A, C, r + 1, bb, w, P, pre);
+      }
+    }
+    if (r == s1) {
+      R w[Q];
+      row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
+      row_steady<R, N>(A, C, r, ba, w, P, pre);
+    }
+  } else {
+    for (int r = s0; r <= s1; ++r) {
+      R d[Q], w[Q];
+      load_row<R, N>(C.s, C.cell(r), A.plane, d);
+      row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+      row_steady<R, N>(A, C, r, d, w, P, pre);
+    }
+  }
+  for (int r = s1 + 1; r <= C.re; ++r) {
+    R d[Q], w[Q];
+    load_row<R, N>(C.s, C.cell(r), A.plane, d);
+    row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+    row_general<R, N>(A, C, r, d, w, P, pre);
+  }
+}
+
 // ------------------------------------------------------------- dispatch ---
 template <typename R, int N, int ORD, bool COMP>
 static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* partials,
@@ -258,6 +537,16 @@ static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* par
       hipLaunchKernelGGL((k_fv_impose<R, N>), dim3((unsigned)((A.nx + 255) / 256), 2), b, 0, st, A);
       break;
     case FV_POPS: hipLaunchKernelGGL((k_fv_pops<R, N>), g, b, 0, st, A, fields); break;
+    case FV_MARCH: {
+      // one tile = 4 wavefronts = 4 consecutive segments of one strip
+      const int tiles = A.strips * ((A.segs + 3) / 4);
+      const dim3 gm((unsigned)((tiles + 7) / 8 * 8));
+      if (A.prefetch)
+        hipLaunchKernelGGL((k_fv_march<R, N, ORD, COMP, true>), gm, b, 0, st, A);
+      else
+        hipLaunchKernelGGL((k_fv_march<R, N, ORD, COMP, false>), gm, b, 0, st, A);
+      break;
+    }
     default: hipLaunchKernelGGL((k_fv_fields<R, N, COMP>), g, b, 0, st, A, fields, partials); break;
   }
   return hipGetLastError();

@@ -31,9 +31,11 @@ struct tvlbm_fv {
   double* d_vol = nullptr;        // [ny]
   double* d_part = nullptr;       // block partials of the totals
   double* d_tot = nullptr;        // 4 totals
+  void* d_wtab = nullptr;         // [4][QMAX] wall constants in dtype
   int nblocks = 0;
   FvArgs<float> af{};
   FvArgs<double> ad{};
+  tvlbm_fv_schedule sched{1, 6, 0};
 };
 
 namespace {
@@ -79,10 +81,31 @@ void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
   A.inv_dx = (R)(2.0 / (v->d.dx + v->d.dx));
   A.cy = (const R*)v->d_cy;
   A.vol = v->d_vol;
+  A.strips = (v->d.nx + 61) / 62;
+  A.seg_rows = v->sched.seg_rows;
+  A.segs = (v->d.ny + A.seg_rows - 1) / A.seg_rows;
+  A.prefetch = v->sched.prefetch;
+  A.wtab = (const R*)v->d_wtab;
   if (A.walls) {
     wall_constants<R>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, A.kap_lo, A.phi_lo);
     wall_constants<R>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, A.kap_hi, A.phi_hi);
   }
+}
+
+template <typename R>
+bool upload_table(void* dev, const FvArgs<R>& A) {
+  R t[4 * QMAX];
+  for (int l = 0; l < QMAX; ++l) {
+    t[l] = A.kap_lo[l];
+    t[QMAX + l] = A.phi_lo[l];
+    t[2 * QMAX + l] = A.kap_hi[l];
+    t[3 * QMAX + l] = A.phi_hi[l];
+  }
+  return hipMemcpy(dev, t, sizeof t, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+bool upload_wall_table(tvlbm_fv* v) {
+  return v->f64 ? upload_table(v->d_wtab, v->ad) : upload_table(v->d_wtab, v->af);
 }
 
 template <typename R>
@@ -178,7 +201,8 @@ int tvlbm_fv_init(const tvlbm_fv_desc* d, tvlbm_fv** out) {
   bool ok = hipMalloc(&v->d_cy, esz * ny) == hipSuccess &&
             hipMalloc(&v->d_vol, sizeof(double) * ny) == hipSuccess &&
             hipMalloc(&v->d_part, sizeof(double) * 4 * v->nblocks) == hipSuccess &&
-            hipMalloc(&v->d_tot, sizeof(double) * 4) == hipSuccess;
+            hipMalloc(&v->d_tot, sizeof(double) * 4) == hipSuccess &&
+            hipMalloc(&v->d_wtab, esz * 4 * QMAX) == hipSuccess;
   if (ok) {
     if (v->f64) {
       ok = hipMemcpy(v->d_cy, v->cyh.data(), 8 * ny, hipMemcpyHostToDevice) == hipSuccess;
@@ -191,6 +215,7 @@ int tvlbm_fv_init(const tvlbm_fv_desc* d, tvlbm_fv** out) {
   if (!ok) { tvlbm_fv_destroy(v); return TVLBM_ENOMEM; }
   fill_args(v, v->af);
   fill_args(v, v->ad);
+  if (!upload_wall_table(v)) { tvlbm_fv_destroy(v); return TVLBM_EHIP; }
   *out = v;
   return TVLBM_OK;
 }
@@ -202,6 +227,7 @@ int tvlbm_fv_destroy(tvlbm_fv* v) {
   hipFree(v->d_vol);
   hipFree(v->d_part);
   hipFree(v->d_tot);
+  hipFree(v->d_wtab);
   delete v;
   return TVLBM_OK;
 }
@@ -248,10 +274,15 @@ int tvlbm_fv_set_fields(tvlbm_fv* v, const void* rho, const void* ux, const void
 int tvlbm_fv_step(tvlbm_fv* v, int32_t nsteps) {
   if (!v || nsteps < 0) return TVLBM_EINVAL;
   for (int32_t s = 0; s < nsteps; ++s) {
-    int rc = run(v, FV_OMEGA, v->buf[v->cur], nullptr);
-    if (rc) return rc;
-    rc = run(v, FV_UPDATE, v->buf[v->cur], v->buf[v->cur ^ 1]);
-    if (rc) return rc;
+    if (v->sched.fused) {
+      const int rc = run(v, FV_MARCH, v->buf[v->cur], v->buf[v->cur ^ 1]);
+      if (rc) return rc;
+    } else {
+      int rc = run(v, FV_OMEGA, v->buf[v->cur], nullptr);
+      if (rc) return rc;
+      rc = run(v, FV_UPDATE, v->buf[v->cur], v->buf[v->cur ^ 1]);
+      if (rc) return rc;
+    }
     v->cur ^= 1;
     ++v->step;
   }
@@ -287,6 +318,25 @@ int tvlbm_fv_moments(tvlbm_fv* v, void* rho, void* ux, void* uy, void* T, double
   if (hipStreamSynchronize(v->st) != hipSuccess && rc == TVLBM_OK) rc = TVLBM_EHIP;
   if (rc == TVLBM_OK && totals) std::memcpy(totals, tot, sizeof tot);
   return rc;
+}
+
+int tvlbm_fv_set_schedule(tvlbm_fv* v, const tvlbm_fv_schedule* s) {
+  if (!v || !s) return TVLBM_EINVAL;
+  if ((s->fused != 0 && s->fused != 1) || s->seg_rows < 0 || s->seg_rows > 65536 ||
+      (s->prefetch != 0 && s->prefetch != 1))
+    return TVLBM_EINVAL;
+  v->sched.fused = s->fused;
+  v->sched.prefetch = s->prefetch;
+  if (s->seg_rows) v->sched.seg_rows = s->seg_rows;
+  fill_args(v, v->af);
+  fill_args(v, v->ad);
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_get_schedule(const tvlbm_fv* v, tvlbm_fv_schedule* s) {
+  if (!v || !s) return TVLBM_EINVAL;
+  *s = v->sched;
+  return TVLBM_OK;
 }
 
 int tvlbm_fv_step_count(const tvlbm_fv* v, int64_t* k) {

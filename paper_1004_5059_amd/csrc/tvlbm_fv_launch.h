@@ -23,10 +23,17 @@ struct FvArgs {
   R kap_hi[QMAX], phi_hi[QMAX];  // and at the top wall
   const R* src;         // d at t
   R* dst;               // d at t + dt
-  R* om;                // Omega at t
+  R* om;                // Omega at t (two-pass schedule)
+  int32_t strips;       // fused march: 62-column strips, one wavefront wide
+  int32_t segs;         // row segments of seg_rows rows
+  int32_t seg_rows;
+  int32_t prefetch;     // load row r+1 while row r is processed
+  const R* wtab;        // device copy of kap_lo, phi_lo, kap_hi, phi_hi [4][QMAX]
 };
 
-enum FvKernel { FV_OMEGA = 0, FV_UPDATE = 1, FV_FIELDS = 2, FV_IMPOSE = 3, FV_POPS = 4 };
+// FV_OMEGA + FV_UPDATE: the two-pass step; FV_MARCH: the fused one-pass step
+enum FvKernel { FV_OMEGA = 0, FV_UPDATE = 1, FV_FIELDS = 2, FV_IMPOSE = 3, FV_POPS = 4,
+                FV_MARCH = 5 };
 
 // FV_FIELDS: fields [4][ny][nx] or null, partials [blocks][4];
 // FV_POPS: fields is the [q][ny][nx] output; FV_IMPOSE acts on A.dst.

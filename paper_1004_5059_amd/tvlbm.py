@@ -176,6 +176,8 @@ def lib():
         "tvlbm_fv_populations": [_vp, _vp],
         "tvlbm_fv_moments": [_vp, _vp, _vp, _vp, _vp, _dp],
         "tvlbm_fv_step_count": [_vp, _i64p],
+        "tvlbm_fv_set_schedule": [_vp, ctypes.c_void_p],
+        "tvlbm_fv_get_schedule": [_vp, ctypes.c_void_p],
         "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
@@ -746,6 +748,22 @@ def tvlbm_fv_moments(h, rho=None, ux=None, uy=None, T=None):
     return np.array(tot[:])
 
 
+class tvlbm_fv_schedule(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
+                ("prefetch", ctypes.c_int32)]
+
+
+def tvlbm_fv_set_schedule(h, fused: int, seg_rows: int = 0, prefetch: int = 1):
+    s = tvlbm_fv_schedule(int(fused), int(seg_rows), int(prefetch))
+    _check(lib().tvlbm_fv_set_schedule(h, ctypes.byref(s)))
+
+
+def tvlbm_fv_get_schedule(h) -> dict:
+    s = tvlbm_fv_schedule()
+    _check(lib().tvlbm_fv_get_schedule(h, ctypes.byref(s)))
+    return {"fused": s.fused, "seg_rows": s.seg_rows, "prefetch": s.prefetch}
+
+
 def tvlbm_fv_step_count(h) -> int:
     k = ctypes.c_int64()
     _check(lib().tvlbm_fv_step_count(h, ctypes.byref(k)))
@@ -832,3 +850,11 @@ class FVSolver:
     @property
     def step_count(self) -> int:
         return tvlbm_fv_step_count(self.h)
+
+    def set_schedule(self, fused: bool = True, seg_rows: int = 0, prefetch: bool = True):
+        """fused: one pass per step (default) or the two-pass schedule;
+        seg_rows: rows per wavefront of the fused pass (0 keeps it)."""
+        tvlbm_fv_set_schedule(self.h, int(fused), seg_rows, int(prefetch))
+
+    def schedule(self) -> dict:
+        return tvlbm_fv_get_schedule(self.h)

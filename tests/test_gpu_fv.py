@@ -1,7 +1,9 @@
 """The finite-volume update on the GPU against its FP64 oracle: periodic
 meshes (uniform and non-uniform in y), walled channels on the paper's tanh
-mesh, every lattice, FP64 within 1e-12 and FP32 within 1e-5 relative, plus
-conservation with the dual-cell weights."""
+mesh, every lattice, both step schedules (the fused one-pass march and the
+two-pass reference), FP64 within 1e-12 and FP32 within 1e-5 relative, plus
+conservation with the dual-cell weights, strip and segment edges of the
+march, and the full 1024 x 1024 mesh."""
 import numpy as np
 import pytest
 
@@ -16,10 +18,17 @@ from paper_1004_5059_amd.tvlbm import LATTICE_ORDER, FVSolver  # noqa: E402
 DT, TAU = 0.05, 0.2
 
 
+FUSED = {"fused": True}
+TWO_PASS = {"fused": False}
+SCHEDS = [pytest.param(FUSED, id="fused"), pytest.param(TWO_PASS, id="two-pass")]
+
+
 def _pair(nx, ny, n, dtype, dy=None, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0),
-          compensated=True):
+          compensated=True, sched=None):
     s = FVSolver(nx, ny, n_gh=n, dtype=dtype, dx=1.0, dt=DT, tau=TAU, dy=dy, walls=walls,
                  wall_lo=wall_lo, wall_hi=wall_hi, compensated=compensated)
+    if sched is not None:
+        s.set_schedule(**sched)
     g = orc.OracleFVGrid(orc.OracleLattice(n, LATTICE_ORDER[n]), nx, ny, dx=1.0, dt=DT, tau=TAU,
                          dy=dy, walls=walls, wall_lo=wall_lo, wall_hi=wall_hi)
     return s, g
@@ -43,11 +52,12 @@ def _check(s, g, steps, tol, fields, noise):
     return fr
 
 
+@pytest.mark.parametrize("sched", SCHEDS)
 @pytest.mark.parametrize("n,dtype,tol", [(4, "f64", 1e-12), (4, "f32", 1e-5), (6, "f64", 1e-12),
-                                         (6, "f32", 1e-5), (3, "f64", 1e-12)])
-def test_periodic_uniform_mesh(n, dtype, tol):
+                                         (6, "f32", 1e-5), (3, "f64", 1e-12), (3, "f32", 1e-5)])
+def test_periodic_uniform_mesh(n, dtype, tol, sched):
     nx, ny = 70, 37
-    s, g = _pair(nx, ny, n, dtype)
+    s, g = _pair(nx, ny, n, dtype, sched=sched)
     _check(s, g, 60, tol, *_inputs(nx, ny, n * n))
     s.close()
 
@@ -69,9 +79,10 @@ def test_periodic_nonuniform_mesh_conserves(dtype, tol):
     s.close()
 
 
+@pytest.mark.parametrize("sched", SCHEDS)
 @pytest.mark.parametrize("n,dtype,tol", [(4, "f64", 1e-12), (4, "f32", 1e-5), (6, "f64", 1e-12),
-                                         (6, "f32", 1e-5)])
-def test_walls_on_the_tanh_mesh(n, dtype, tol):
+                                         (6, "f32", 1e-5), (3, "f64", 1e-12)])
+def test_walls_on_the_tanh_mesh(n, dtype, tol, sched):
     """Walls at the first and last mesh rows (top moving, hotter), rows from
     the hyperbolic-tangent stretching of Sec. VIII (41 points, beta 2.3),
     scaled to spacings of 0.31 .. 7.0 mesh units so that c dt / dy stays
@@ -82,7 +93,8 @@ def test_walls_on_the_tanh_mesh(n, dtype, tol):
     y = inputs.tanh_mesh(10.0, 40, 2.3)
     dy = np.diff(y) * 12.0
     ny = len(y)
-    s, g = _pair(nx, ny, n, dtype, dy=dy, walls=True, wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1))
+    s, g = _pair(nx, ny, n, dtype, dy=dy, walls=True, wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1),
+                 sched=sched)
     _check(s, g, 100, tol, *_inputs(nx, ny, n * n, seed=5))
     f = to_np(s.populations())
     cy = g.lat.xi[:, 1]
@@ -103,3 +115,50 @@ def test_compensated_and_plain_sums_agree():
         outs.append(to_np(s.populations()))
         s.close()
     assert rel_inf(outs[0], outs[1]) <= 1e-5
+
+
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("nx,ny,seg_rows,prefetch", [
+    (2, 5, 1, True), (5, 9, 3, False), (61, 20, 7, True), (62, 21, 64, True),
+    (63, 17, 4, False), (125, 33, 16, True), (124, 3, 2, True)])
+def test_fused_strip_and_segment_edges(nx, ny, seg_rows, prefetch, walls):
+    """Widths around the 62-column strips (one strip, one plus a column, a
+    sliver), tiny meshes whose strips wrap several times, segments of 1 row
+    up to longer than the mesh, with and without the row prefetch."""
+    dy = np.random.default_rng(nx + ny).uniform(0.6, 1.4, ny - 1 if walls else ny)
+    s, g = _pair(nx, ny, 4, "f64", dy=dy, walls=walls, wall_lo=(0.0, 1.0), wall_hi=(0.03, 1.05),
+                 sched={"fused": True, "seg_rows": seg_rows, "prefetch": prefetch})
+    assert s.schedule() == {"fused": 1, "seg_rows": seg_rows, "prefetch": int(prefetch)}
+    _check(s, g, 12, 1e-12, *_inputs(nx, ny, 16, seed=11))
+    s.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_full_size_mesh(dtype, tol):
+    """The timed configuration: 1024 x 1024 walled tanh mesh, D2Q16, the
+    default fused schedule, every output compared after 3 steps."""
+    size = 1024
+    y = inputs.tanh_mesh(10.0, size - 1, 2.3)
+    dy = np.diff(y)
+    dy = dy * (0.5 / dy.min())
+    s, g = _pair(size, size, 4, dtype, dy=dy, walls=True, wall_lo=(0.0, 1.0),
+                 wall_hi=(0.04, 1.1))
+    fields = inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1)
+    noise = inputs.population_noise(16, size, size, amp=1e-4, seed=2)
+    _check(s, g, 3, tol, fields, noise)
+    s.close()
+
+
+def test_schedules_agree_over_many_steps():
+    nx, ny = 96, 80
+    y = inputs.tanh_mesh(10.0, ny - 1, 2.3)
+    dy = np.diff(y) * (0.4 / np.diff(y).min())
+    outs = []
+    for sched in (FUSED, TWO_PASS):
+        s, _ = _pair(nx, ny, 4, "f64", dy=dy, walls=True, wall_lo=(0.0, 1.0),
+                     wall_hi=(0.05, 1.1), sched=sched)
+        s.set_fields(*_inputs(nx, ny, 16, seed=13)[0])
+        s.step(400)
+        outs.append(to_np(s.populations()))
+        s.close()
+    assert rel_inf(outs[0], outs[1]) <= 1e-12

@@ -199,3 +199,10 @@ def test_fv_descriptor_layout_matches_header():
     assert d.ld.offset == 24 and d.dx.offset == 32 and d.collide.offset == 56
     assert d.wall_lo_ux.offset == 64 and d.dy.offset == 96 and d.omega.offset == 120
     assert ctypes.sizeof(d) == 136
+
+
+def test_fv_schedule_rejects_null_handles():
+    s = T.tvlbm_fv_schedule(1, 16, 1)
+    assert T.lib().tvlbm_fv_set_schedule(None, ctypes.byref(s)) == T.TVLBM_EINVAL
+    assert T.lib().tvlbm_fv_get_schedule(None, ctypes.byref(s)) == T.TVLBM_EINVAL
+    assert ctypes.sizeof(T.tvlbm_fv_schedule) == 12
