@@ -74,7 +74,7 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
 
 
 def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls: bool = True,
-           sched: dict | None = None):
+           sched="auto"):
     """The finite-volume update, eq.(FVLB), on a size x size mesh: walls at the
     first and last rows on the hyperbolic-tangent mesh of Sec. VIII scaled to
     spacings 0.5 .. ~2.3 (or periodic and uniform), dt = 0.05, tau = 0.2."""
@@ -91,10 +91,15 @@ def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls
         dy = dy * (0.5 / dy.min())
     s = FVSolver(size, size, n_gh=n, dtype=dtype, dx=1.0, dt=0.05, tau=0.2, dy=dy, walls=walls,
                  wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1), device="cuda:0")
-    if sched:
+    s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
+    if sched == "auto":
+        from paper_1004_5059_amd.autotune import autotune_fv
+
+        autotune_fv(s)
+        s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
+    elif sched:
         s.set_schedule(**sched)
     schedule = s.schedule()
-    s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
     s.step(warmup)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
@@ -312,6 +317,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
     ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume legs")
     ap.add_argument("--fv-only", action="store_true", help="run only the finite-volume legs")
+    ap.add_argument("--fv-size", type=int, default=1024, help="mesh size of the finite-volume legs")
     ap.add_argument("--batched-load-only", action="store_true",
                     help="batched leg: full-load steps only, no steady solves")
     args = ap.parse_args()
@@ -330,13 +336,13 @@ def main():
     fv = None
     if not args.no_fv:
         fv_steps = max(20, args.steps // 4)
-        fv = {"d2q16_f32_walls": leg("FV D2Q16", run_fv, 4, args.size, fv_steps, 10),
-              "d2q16_f32_walls_two_pass": leg("FV D2Q16 two-pass", run_fv, 4, args.size,
+        fv = {"d2q16_f32_walls": leg("FV D2Q16", run_fv, 4, args.fv_size, fv_steps, 10),
+              "d2q16_f32_walls_two_pass": leg("FV D2Q16 two-pass", run_fv, 4, args.fv_size,
                                               fv_steps, 10, "f32", True, {"fused": False}),
-              "d2q16_f32_periodic": leg("FV D2Q16 periodic", run_fv, 4, args.size, fv_steps, 10,
-                                        "f32", False),
-              "d2q36_f32_walls": leg("FV D2Q36", run_fv, 6, args.size, fv_steps // 2, 5),
-              "d2q16_f64_walls": leg("FV D2Q16 FP64", run_fv, 4, args.size, fv_steps // 2, 5,
+              "d2q16_f32_periodic": leg("FV D2Q16 periodic", run_fv, 4, args.fv_size, fv_steps,
+                                        10, "f32", False),
+              "d2q36_f32_walls": leg("FV D2Q36", run_fv, 6, args.fv_size, fv_steps // 2, 5),
+              "d2q16_f64_walls": leg("FV D2Q16 FP64", run_fv, 4, args.fv_size, fv_steps // 2, 5,
                                      "f64")}
         if args.fv_only:
             print(json.dumps({"fv": fv}), flush=True)

@@ -153,3 +153,35 @@ def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: st
     return {"shapes": dict(choice),
             "tuning": {"prefetch": pf, "tail_active": tail_active, "tail_width": best[0],
                        "tail_rows": best[1]}}
+
+
+FV_SEG_ROWS = [4, 5, 6, 7, 8, 10, 12, 16]
+
+
+def autotune_fv(solver, steps: int = 20, reps: int = 2):
+    """Fastest schedule of the fused finite-volume step (rows per wavefront
+    segment x row prefetch) for `solver` (an FVSolver; advances its state).
+    Every schedule computes the same update up to rounding order, so the
+    choice only affects speed.  Returns (schedule dict, {label: ms/step})."""
+    import torch
+
+    times = {}
+    for pf in (False, True):
+        for sr in FV_SEG_ROWS:
+            solver.set_schedule(True, sr, pf)
+            solver.step(2)
+            best = float("inf")
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(solver.stream)
+                solver.step(steps)
+                b.record(solver.stream)
+                b.synchronize()
+                best = min(best, a.elapsed_time(b) / steps)
+            times[f"seg{sr}{'_pf' if pf else ''}"] = best
+    label = min(times, key=times.get)
+    sr = int(label[3:].split("_")[0])
+    pf = label.endswith("_pf")
+    solver.set_schedule(True, sr, pf)
+    return solver.schedule(), times

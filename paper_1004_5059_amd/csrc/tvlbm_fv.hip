@@ -340,16 +340,21 @@ __device__ __forceinline__ void row_omega(const Lat<R>& L, bool collide, const R
   }
 }
 
-// Per-wavefront constants of the march.
+// Per-wavefront constants of the march.  A segment's wavefront marches
+// down (dir = +1) or up (dir = -1) its rows; neighbouring segments march in
+// opposite directions, so the two reads of every halo row fall together and
+// the second one hits L2.
 template <typename R>
 struct MarchC {
   rsrc_t s, dst;
   uint32_t ld, col;
-  int ny, y0, y1, rs, re;
+  int ny, y0, y1, first, last, dir;
   bool walls, out_lane;
   R c1, c2, hx8, hh8;
   __device__ int wrap(int r) const { return r < 0 ? r + ny : (r >= ny ? r - ny : r); }
   __device__ uint32_t cell(int r) const { return (uint32_t)wrap(r) * ld + col; }
+  __device__ bool out(int r) const { return r >= y0 && r < y1; }
+  __device__ bool wall(int r) const { return walls && (r == 0 || r == ny - 1); }
 };
 
 // Scaled row quantities of population l: a8 = 8 a, e = E (= e / 8).
@@ -361,18 +366,23 @@ __device__ __forceinline__ void row_quant(const MarchC<R>& C, R hxa, R d, R w, R
   e = fmaR(C.c1, wm + wp, fmaR(C.c2, w, -(hxa * (dp - dm))));
 }
 
-// An interior row r between interior rows: finish row r-1 (store), carry
-// row r in P, start row r+1 in pre.
+// The marching form of d'_j = d_j + 6 E_j + E_{j-1} + E_{j+1}
+// - (h_j / 8)(a8_{j+1} - a8_{j-1}): with p = r - dir the row finished when
+// row r arrives and n = r + dir the row started,
+//   d'_p = P + E_r - dir (h_p / 8) a8_r,   P <- d_r + 6 E_r + pre,
+//   pre  <- E_r + dir (h_n / 8) a8_r.
+// An interior row between interior rows: finish p (store), carry r, start n.
 template <typename R, int N>
 __device__ __forceinline__ void row_steady(const FvArgs<R>& A, const MarchC<R>& C, int r,
                                            const R (&d)[N * N], const R (&w)[N * N],
                                            R (&P)[N * N], R (&pre)[N * N]) {
   const Lat<R>& L = A.lat;
-  const R hp = C.hh8 * A.cy[C.wrap(r - 1)], hn = C.hh8 * A.cy[C.wrap(r + 1)];
+  const R sh = C.dir > 0 ? C.hh8 : -C.hh8;
+  const R hp = sh * A.cy[C.wrap(r - C.dir)], hn = sh * A.cy[C.wrap(r + C.dir)];
   R hpb[N], hnb[N];
 #pragma unroll
   for (int b = 0; b < N; ++b) { hpb[b] = hp * L.x[b]; hnb[b] = hn * L.x[b]; }
-  const uint32_t cprev = C.cell(r - 1);
+  const uint32_t cprev = C.cell(r - C.dir);
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const R hxa = C.hx8 * L.x[a];
@@ -391,23 +401,22 @@ __device__ __forceinline__ void row_steady(const FvArgs<R>& A, const MarchC<R>& 
 
 // Any row (segment ends, wall rows): E-weights 1 in the interior and 2 (1/4
 // unscaled) towards a wall row; a wall row's own a-term is +h a at the
-// bottom and -h a at the top (one-sided difference); wall rows are
-// re-emitted, eq.(IMPOSITION), before they are stored.
+// bottom and -h a at the top (one-sided difference, eq.(FVLB2)); wall rows
+// are re-emitted, eq.(IMPOSITION), before they are stored.  A wall row that
+// ends the march is finished on arrival.
 template <typename R, int N>
 __device__ __forceinline__ void row_general(const FvArgs<R>& A, const MarchC<R>& C, int r,
                                             const R (&d)[N * N], const R (&w)[N * N],
                                             R (&P)[N * N], R (&pre)[N * N]) {
   const Lat<R>& L = A.lat;
-  const int ny = C.ny;
-  const bool prev_out = r - 1 >= C.y0 && r - 1 < C.y1 && !(C.walls && r - 1 == ny - 1);
-  const bool prev_lo = C.walls && r - 1 == 0;
-  const bool cur_out = r >= C.y0 && r < C.y1;
-  const bool cur_lo = C.walls && r == 0, cur_hi = C.walls && r == ny - 1;
-  const bool next_hi = C.walls && r + 1 == ny - 1;
-  const R hp = C.hh8 * A.cy[C.wrap(r - 1)], hn = C.hh8 * A.cy[C.wrap(r + 1)];
+  const int ny = C.ny, p = r - C.dir, n = r + C.dir;
+  const bool prev_out = r != C.first && C.out(p);
+  const bool cur_final = C.out(r) && r == C.last;
+  const R sh = C.dir > 0 ? C.hh8 : -C.hh8;
+  const R hp = sh * A.cy[C.wrap(p)], hn = sh * A.cy[C.wrap(n)];
   const R hc = C.hh8 * A.cy[C.wrap(r)];
-  const R bprev = prev_lo ? R(2) : R(1), bnext = next_hi ? R(2) : R(1);
-  const R kc = cur_lo ? hc : (cur_hi ? -hc : R(0));
+  const R bprev = C.wall(p) ? R(2) : R(1), bnext = C.wall(n) ? R(2) : R(1);
+  const R kc = (C.walls && r == 0) ? hc : ((C.walls && r == ny - 1) ? -hc : R(0));
   R o[N * N];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
@@ -417,17 +426,17 @@ __device__ __forceinline__ void row_general(const FvArgs<R>& A, const MarchC<R>&
       const int l = a * N + b;
       R a8, e;
       row_quant<R, N>(C, hxa, d[l], w[l], a8, e);
-      o[l] = fmaR(-(hp * L.x[b]), a8, fmaR(bprev, e, P[l]));          // row r-1
+      o[l] = fmaR(-(hp * L.x[b]), a8, fmaR(bprev, e, P[l]));          // row p
       P[l] = fmaR(kc * L.x[b], a8, fmaR(R(6), e, d[l]) + pre[l]);     // row r
-      pre[l] = fmaR(hn * L.x[b], a8, bnext * e);                      // row r+1
+      pre[l] = fmaR(hn * L.x[b], a8, bnext * e);                      // row n
     }
   }
   if (prev_out) {
-    if (prev_lo) impose<R, N>(L, A.wtab, false, o);
-    if (C.out_lane) store_row<R, N>(C.dst, C.cell(r - 1), A.plane, o);
+    if (C.wall(p)) impose<R, N>(L, A.wtab + (p == 0 ? 0 : 2 * QMAX), p != 0, o);
+    if (C.out_lane) store_row<R, N>(C.dst, C.cell(p), A.plane, o);
   }
-  if (cur_out && cur_hi) {
-    impose<R, N>(L, A.wtab + 2 * QMAX, true, P);
+  if (cur_final) {
+    impose<R, N>(L, A.wtab + (r == 0 ? 0 : 2 * QMAX), r != 0, P);
     if (C.out_lane) store_row<R, N>(C.dst, C.cell(r), A.plane, P);
   }
 }
@@ -461,63 +470,73 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   // Scaled row quantities: a8 = 8 a = (d_{i-1} + d_{i+1}) + 6 d and
   // E = e / 8 = c1 (W_{i-1} + W_{i+1}) + c2 W - hx8_a (d_{i+1} - d_{i-1}),
   // W = w_l feq-deviation - d = tau Omega, c1 = dt / (64 tau),
-  // c2 = 3 dt / (32 tau), hx8_a = dt c_x / (16 dx); then
-  //   d'_j = d_j + 6 E_j + E_{j-1} + E_{j+1} - (h_j / 8)(a8_{j+1} - a8_{j-1}).
+  // c2 = 3 dt / (32 tau), hx8_a = dt c_x / (16 dx), h_j / 8 = hh8 c_y cy_j.
   C.c1 = A.dt * A.inv_tau * R(1.0 / 64.0);
   C.c2 = A.dt * A.inv_tau * R(3.0 / 32.0);
   C.hx8 = A.dt * A.inv_dx * R(1.0 / 16.0);
-  C.hh8 = A.dt * R(1.0 / 16.0);  // h_j / (8 c_y) = dt cy_j / 16
-  C.rs = C.walls ? max(C.y0 - 1, 0) : C.y0 - 1;
-  C.re = C.walls ? min(C.y1, ny - 1) : C.y1;
-  // rows s0..s1 are interior rows between interior rows of this segment
-  int s0 = C.y0 + 1, s1 = min(C.re - 1, C.y1 - 1);
+  C.hh8 = A.dt * R(1.0 / 16.0);
+  // rows rs..re: the segment and its halo (wall rows have none outside)
+  const int rs = C.walls ? max(C.y0 - 1, 0) : C.y0 - 1;
+  const int re = C.walls ? min(C.y1, ny - 1) : C.y1;
+  C.dir = (seg & 1) ? -1 : 1;
+  C.first = C.dir > 0 ? rs : re;
+  C.last = C.dir > 0 ? re : rs;
+  // steady rows: previous and next rows are interior rows of the march
+  int s0, s1;
+  if (C.dir > 0) { s0 = max(C.y0 + 1, rs + 1); s1 = min(C.y1 - 1, re - 1); }
+  else { s0 = max(C.y0, rs + 1); s1 = min(C.y1 - 2, re - 1); }
   if (C.walls) { s0 = max(s0, 2); s1 = min(s1, ny - 3); }
-  const bool steady = s0 <= s1;
+  const int nst = s1 >= s0 ? s1 - s0 + 1 : 0;
+  const int sa = C.dir > 0 ? s0 : s1;  // first steady row in march order
 
   R P[Q], pre[Q];
 #pragma unroll
   for (int l = 0; l < Q; ++l) { P[l] = R(0); pre[l] = R(0); }
-  const int g_end = steady ? s0 : C.re + 1;
-  for (int r = C.rs; r < g_end; ++r) {
+  // rows before the steady run (all rows if there is none)
+  const int ng = nst ? (sa - C.first) * C.dir : (re - rs + 1);
+  int r = C.first;
+  for (int k = 0; k < ng; ++k, r += C.dir) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
     row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
     row_general<R, N>(A, C, r, d, w, P, pre);
   }
-  if (!steady) return;
+  if (!nst) return;
   if constexpr (PF) {
-    // two row buffers in turn: row r+1 loads while row r is processed
+    // two row buffers in turn: the next row loads while this one is used
     R ba[Q], bb[Q];
-    load_row<R, N>(C.s, C.cell(s0), A.plane, ba);
-    int r = s0;
-    for (; r + 1 <= s1; r += 2) {
-      load_row<R, N>(C.s, C.cell(r + 1), A.plane, bb);
+    load_row<R, N>(C.s, C.cell(r), A.plane, ba);
+    int k = 0;
+    for (; k + 1 < nst; k += 2, r += 2 * C.dir) {
+      load_row<R, N>(C.s, C.cell(r + C.dir), A.plane, bb);
       {
         R w[Q];
         row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
         row_steady<R, N>(A, C, r, ba, w, P, pre);
       }
-      if (r + 2 <= s1) load_row<R, N>(C.s, C.cell(r + 2), A.plane, ba);
+      if (k + 2 < nst) load_row<R, N>(C.s, C.cell(r + 2 * C.dir), A.plane, ba);
       {
         R w[Q];
         row_omega<R, N, ORD, COMP>(L, A.collide, bb, w);
-        row_steady<R, N>(A, C, r + 1, bb, w, P, pre);
+        row_steady<R, N>(A, C, r + C.dir, bb, w, P, pre);
       }
     }
-    if (r == s1) {
+    if (k < nst) {
       R w[Q];
       row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
       row_steady<R, N>(A, C, r, ba, w, P, pre);
+      r += C.dir;
     }
   } else {
-    for (int r = s0; r <= s1; ++r) {
+    for (int k = 0; k < nst; ++k, r += C.dir) {
       R d[Q], w[Q];
       load_row<R, N>(C.s, C.cell(r), A.plane, d);
       row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
       row_steady<R, N>(A, C, r, d, w, P, pre);
     }
   }
-  for (int r = s1 + 1; r <= C.re; ++r) {
+  // rows after the steady run
+  for (; r != C.last + C.dir; r += C.dir) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
     row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
