@@ -292,19 +292,23 @@ __device__ __forceinline__ void load_row(rsrc_t s, uint32_t c, int64_t plane, R*
 }
 
 // eq.(IMPOSITION) at a wall point of the new state (tab: kap then phi of
-// that wall, in device memory so that the constants are loaded only here).
+// that wall, FP64 in device memory so that they are loaded only here).  The
+// incoming flux and the re-emitted deviations are formed in FP64 and rounded
+// once (FP32 copies of the constant kap, phi would add the same rounding to
+// the wall mass flux every step).
 template <typename R, int N>
-__device__ __forceinline__ void impose(const Lat<R>& L, const R* __restrict__ tab, bool top, R* o) {
-  R m = R(0);
+__device__ __forceinline__ void impose(const Lat<R>& L, const double* __restrict__ tab, bool top,
+                                       R* o) {
+  double m = 0.0;
 #pragma unroll
   for (int l = 0; l < N * N; ++l) {
     const R cn = top ? -L.x[l % N] : L.x[l % N];
-    if (cn <= R(0)) m = fmaR(-cn, o[l], m);
+    if (cn <= R(0)) m = __builtin_fma(-(double)L.xd[l % N] * (top ? -1.0 : 1.0), (double)o[l], m);
   }
 #pragma unroll
   for (int l = 0; l < N * N; ++l) {
     const R cn = top ? -L.x[l % N] : L.x[l % N];
-    if (cn > R(0)) o[l] = fmaR(tab[QMAX + l], m, tab[l]);
+    if (cn > R(0)) o[l] = (R)__builtin_fma(tab[QMAX + l], m, tab[l]);
   }
 }
 

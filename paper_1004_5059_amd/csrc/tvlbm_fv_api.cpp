@@ -85,27 +85,18 @@ void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
   A.seg_rows = v->sched.seg_rows;
   A.segs = (v->d.ny + A.seg_rows - 1) / A.seg_rows;
   A.prefetch = v->sched.prefetch;
-  A.wtab = (const R*)v->d_wtab;
+  A.wtab = (const double*)v->d_wtab;
   if (A.walls) {
     wall_constants<R>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, A.kap_lo, A.phi_lo);
     wall_constants<R>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, A.kap_hi, A.phi_hi);
   }
 }
 
-template <typename R>
-bool upload_table(void* dev, const FvArgs<R>& A) {
-  R t[4 * QMAX];
-  for (int l = 0; l < QMAX; ++l) {
-    t[l] = A.kap_lo[l];
-    t[QMAX + l] = A.phi_lo[l];
-    t[2 * QMAX + l] = A.kap_hi[l];
-    t[3 * QMAX + l] = A.phi_hi[l];
-  }
-  return hipMemcpy(dev, t, sizeof t, hipMemcpyHostToDevice) == hipSuccess;
-}
-
 bool upload_wall_table(tvlbm_fv* v) {
-  return v->f64 ? upload_table(v->d_wtab, v->ad) : upload_table(v->d_wtab, v->af);
+  double t[4 * QMAX];
+  wall_constants<double>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, t, t + QMAX);
+  wall_constants<double>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, t + 2 * QMAX, t + 3 * QMAX);
+  return hipMemcpy(v->d_wtab, t, sizeof t, hipMemcpyHostToDevice) == hipSuccess;
 }
 
 template <typename R>
@@ -202,7 +193,7 @@ int tvlbm_fv_init(const tvlbm_fv_desc* d, tvlbm_fv** out) {
             hipMalloc(&v->d_vol, sizeof(double) * ny) == hipSuccess &&
             hipMalloc(&v->d_part, sizeof(double) * 4 * v->nblocks) == hipSuccess &&
             hipMalloc(&v->d_tot, sizeof(double) * 4) == hipSuccess &&
-            hipMalloc(&v->d_wtab, esz * 4 * QMAX) == hipSuccess;
+            hipMalloc(&v->d_wtab, sizeof(double) * 4 * QMAX) == hipSuccess;
   if (ok) {
     if (v->f64) {
       ok = hipMemcpy(v->d_cy, v->cyh.data(), 8 * ny, hipMemcpyHostToDevice) == hipSuccess;

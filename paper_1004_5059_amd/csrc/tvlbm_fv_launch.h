@@ -28,7 +28,7 @@ struct FvArgs {
   int32_t segs;         // row segments of seg_rows rows
   int32_t seg_rows;
   int32_t prefetch;     // load row r+1 while row r is processed
-  const R* wtab;        // device copy of kap_lo, phi_lo, kap_hi, phi_hi [4][QMAX]
+  const double* wtab;   // FP64 kap_lo, phi_lo, kap_hi, phi_hi [4][QMAX] (device)
 };
 
 // FV_OMEGA + FV_UPDATE: the two-pass step; FV_MARCH: the fused one-pass step

@@ -162,3 +162,60 @@ def test_schedules_agree_over_many_steps():
         outs.append(to_np(s.populations()))
         s.close()
     assert rel_inf(outs[0], outs[1]) <= 1e-12
+
+
+def _refined_couette(dtype, n=4):
+    """Sec. VIII: L_x x L_y = 0.2 x 10, N_x = 2 (dx = 0.1, periodic), N_y = 60
+    spacings of the tanh mesh (beta = 2.3, 0.016631 at the walls), walls at
+    u = -0.1 / +0.1 and T = 1, tau = 0.01, dt = 0.005."""
+    y = inputs.tanh_mesh(10.0, 60, 2.3)
+    s = FVSolver(2, len(y), n_gh=n, dtype=dtype, dx=0.1, dt=0.005, tau=0.01, dy=np.diff(y),
+                 walls=True, wall_lo=(-0.1, 1.0), wall_hi=(0.1, 1.0))
+    return s, y
+
+
+def test_refined_couette_parity():
+    s, y = _refined_couette("f64")
+    g = orc.OracleFVGrid(orc.OracleLattice(4, 3), 2, len(y), dx=0.1, dt=0.005, tau=0.01,
+                         dy=np.diff(y), walls=True, wall_lo=(-0.1, 1.0), wall_hi=(0.1, 1.0))
+    one = np.ones((len(y), 2))
+    s.set_fields(one, 0 * one, 0 * one, one)
+    f = g.set_fields(one, 0 * one, 0 * one, one)
+    s.step(20000)
+    assert rel_inf(to_np(s.populations()), g.run(f, 20000)) <= 1e-11
+    s.close()
+
+
+def test_refined_couette_reaches_the_stationary_profile():
+    """From rest, 2.4e6 steps (t = 12000, ~12 e-folds of the slowest shear
+    mode nu (pi/L)^2 with nu = tau T) in FP32: the stationary profile of the
+    BGK gas (Prandtl number 1, c_p = 2 in two dimensions) between walls at
+    -U and +U with equal temperatures is u = U (2 eta - 1) and
+    T = 1 + (2U)^2 eta (1 - eta) / 4, eta = y / L_y (momentum and energy
+    balance: mu u' constant, kappa T'' = -mu u'^2 with kappa = c_p mu / Pr).
+    The second-order scheme meets it within 0.5% of U and 1% of the peak
+    heating (its residual is the wall slip at this Knudsen number); mass is
+    conserved with the dual-cell weights to FP32 rounding: ~6e-11 per step
+    here, a bias rather than a random walk because the rounding of the
+    equilibrium sums repeats on this nearly uniform state (the FP64 path is
+    the one for runs this long).  One-row segments: the 2 x 61 mesh is
+    latency bound."""
+    s, y = _refined_couette("f32")
+    s.set_schedule(True, 1, True)
+    one = np.ones((len(y), 2))
+    s.set_fields(one, 0 * one, 0 * one, one)
+    _, t0 = s.moments()
+    s.step(2_400_000)
+    F, t1 = s.moments()
+    F = to_np(F)
+    eta = y / 10.0
+    u, T = F[1][:, 0], F[3][:, 0]
+    assert np.max(np.abs(u - 0.1 * (2 * eta - 1))) <= 0.005 * 0.1
+    assert np.max(np.abs(T - (1 + 0.01 * eta * (1 - eta)))) <= 0.01 * 0.0025
+    assert np.max(np.abs(F[1][:, 1] - u)) <= 1e-7  # uniform along x
+    drift = abs(t1[0] - t0[0]) / t0[0]
+    print(f"refined Couette: max|u-ua|/U {np.max(np.abs(u - 0.1 * (2 * eta - 1))) / 0.1:.3e} "
+          f"max|T-Ta|/dT {np.max(np.abs(T - (1 + 0.01 * eta * (1 - eta)))) / 0.0025:.3e} "
+          f"mass drift {drift:.2e}")
+    assert drift <= 5e-4
+    s.close()
