@@ -74,7 +74,7 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
 
 
 def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls: bool = True,
-           sched="auto"):
+           sched="auto", tau_g: float = 0.0, pscale: bool = False):
     """The finite-volume update, eq.(FVLB), on a size x size mesh: walls at the
     first and last rows on the hyperbolic-tangent mesh of Sec. VIII scaled to
     spacings 0.5 .. ~2.3 (or periodic and uniform), dt = 0.05, tau = 0.2."""
@@ -91,6 +91,7 @@ def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls
         dy = dy * (0.5 / dy.min())
     s = FVSolver(size, size, n_gh=n, dtype=dtype, dx=1.0, dt=0.05, tau=0.2, dy=dy, walls=walls,
                  wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1), device="cuda:0")
+    s.set_prandtl(tau_g, pscale)
     s.set_fields(*inputs.smoothed_density_fields(size, size, std=0.01, t_amp=0.05, seed=1))
     if sched == "auto":
         from paper_1004_5059_amd.autotune import autotune_fv
@@ -119,7 +120,8 @@ def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls
             "achieved_gbs": round(bytes_per_step / (ms / 1e3 / steps) / 1e9, 1),
             "frac": round(bytes_per_step / (ms / 1e3 / steps) / 1e9 / HBM_PEAK_GBS, 4),
             "finite": bool(np.isfinite(tot).all()), "walls": walls, "dtype": dtype,
-            "lattice": f"D2Q{q}", "schedule": schedule}
+            "lattice": f"D2Q{q}", "schedule": schedule,
+            **({"tau_g": tau_g, "pressure_scaled": pscale} if tau_g > 0 or pscale else {})}
 
 
 def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100,
@@ -341,6 +343,8 @@ def main():
                                               fv_steps, 10, "f32", True, {"fused": False}),
               "d2q16_f32_periodic": leg("FV D2Q16 periodic", run_fv, 4, args.fv_size, fv_steps,
                                         10, "f32", False),
+              "d2q16_f32_walls_prandtl": leg("FV D2Q16 Pr 1/5", run_fv, 4, args.fv_size, fv_steps,
+                                             10, "f32", True, "auto", 0.1, True),
               "d2q36_f32_walls": leg("FV D2Q36", run_fv, 6, args.fv_size, fv_steps // 2, 5),
               "d2q16_f64_walls": leg("FV D2Q16 FP64", run_fv, 4, args.fv_size, fv_steps // 2, 5,
                                      "f64")}

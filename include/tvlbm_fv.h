@@ -90,6 +90,21 @@ typedef struct tvlbm_fv_schedule {
   int32_t prefetch;
 } tvlbm_fv_schedule;
 int tvlbm_fv_set_schedule(tvlbm_fv *fv, const tvlbm_fv_schedule *s);
+
+/* Non-unit Prandtl number, eq.(FINAL) / eq.(OMEGAFVLB), and the
+ * pressure-rescaled relaxation times of Sec. VIII.  tau_g > 0 (finite) adds
+ * to the collision term
+ *   -(1/tau_g) feq_l / (rho T^2) Pi : (c_l - u)(c_l - u),
+ *   Pi_ij = sum_l (f_l - feq_l)(c_l - u)_i (c_l - u)_j,
+ * which gives the viscosity eta = c_v rho T tau tau_g / (2 tau + tau_g)
+ * (c_v = D/2) and leaves the conductivity c_P rho T tau, i.e. Prandtl
+ * number c_v tau_g / (2 tau + tau_g) in two dimensions.  The sign is the one
+ * that makes this viscosity hold: the printed plus sign would let Pi grow
+ * for tau_g < 2 tau.  tau_g <= 0 or infinite: single relaxation (default).
+ * pressure_scaled = 1: tau -> tau / p and tau_g -> tau_g / p with the local
+ * p = rho T.  No effect without collisions.  Applies to later steps.
+ * EINVAL on a null handle, NaN or a flag other than 0 / 1. */
+int tvlbm_fv_set_prandtl(tvlbm_fv *fv, double tau_g, int32_t pressure_scaled);
 int tvlbm_fv_get_schedule(const tvlbm_fv *fv, tvlbm_fv_schedule *s);
 
 #ifdef __cplusplus

@@ -140,6 +140,8 @@ def lib():
         _lib.orc_fv_dual.restype = ctypes.c_double
         _lib.orc_fv_totals.argtypes = [L, FG, _dp, _dp]
         _lib.orc_fv_totals.restype = None
+        _lib.orc_fv_set_prandtl.argtypes = [FG, ctypes.c_double, ctypes.c_int]
+        _lib.orc_fv_set_prandtl.restype = None
     return _lib
 
 
@@ -288,6 +290,8 @@ class FVGrid(ctypes.Structure):
         ("dy", _dp),
         ("emit_lo", ctypes.c_double * QMAX),
         ("emit_hi", ctypes.c_double * QMAX),
+        ("tau_g", ctypes.c_double),
+        ("pscale", ctypes.c_int),
     ]
 
 
@@ -296,7 +300,8 @@ class OracleFVGrid:
     are [q][ny][nx] float64 over the mesh points."""
 
     def __init__(self, lat: OracleLattice, nx: int, ny: int, dx: float, dt: float, tau: float,
-                 dy=None, collide=True, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0)):
+                 dy=None, collide=True, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0),
+                 tau_g: float = 0.0, pscale: bool = False):
         self.lat = lat
         self.nx, self.ny = nx, ny
         self.g = FVGrid()
@@ -308,6 +313,7 @@ class OracleFVGrid:
             lib().orc_fv_free(ctypes.byref(self.g))
             raise ValueError("invalid finite-volume mesh")
         self.dual = np.array([lib().orc_fv_dual(ctypes.byref(self.g), j) for j in range(ny)])
+        lib().orc_fv_set_prandtl(ctypes.byref(self.g), float(tau_g), int(pscale))
 
     def __del__(self):
         try:

@@ -47,6 +47,11 @@ int orc_fv_init(const orc_lattice *L, orc_fv_grid *G, int nx, int ny, double dx,
   return 0;
 }
 
+void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale) {
+  G->tau_g = tau_g;
+  G->pscale = pscale;
+}
+
 void orc_fv_free(orc_fv_grid *G) {
   free(G->dy);
   G->dy = NULL;
@@ -108,7 +113,30 @@ static void collision_term(const orc_lattice *L, const orc_fv_grid *G, const dou
     double r, vx, vy, T, feq[ORC_QMAX];
     orc_moments(L, f + c, plane, &r, &vx, &vy, &T);
     orc_feq(L, r, vx, vy, T, feq);
-    for (int l = 0; l < L->q; ++l) om[l * plane + c] = -(f[l * plane + c] - feq[l]) / G->tau;
+    /* pressure-rescaled relaxation times: tau / p, tau_g / p */
+    const double ps = G->pscale ? r * T : 1.0;
+    for (int l = 0; l < L->q; ++l) om[l * plane + c] = -ps * (f[l * plane + c] - feq[l]) / G->tau;
+    if (G->tau_g > 0.0) {
+      /* eq.(FINAL): Pi from the non-equilibrium part, central velocities.
+       * The term enters with a minus sign: contracted with (c-u)(c-u) it
+       * changes Pi at the rate -2 Pi / tau_g, so that the stress relaxes at
+       * 1/tau + 2/tau_g and the viscosity is the paper's
+       * c_v rho T tau tau_g / (2 tau + tau_g); the printed plus sign would
+       * make the stress grow whenever tau_g < 2 tau. */
+      double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+      for (int l = 0; l < L->q; ++l) {
+        const double ne = f[l * plane + c] - feq[l];
+        const double X = L->xi[l][0] - vx, Y = L->xi[l][1] - vy;
+        pxx += ne * X * X;
+        pxy += ne * X * Y;
+        pyy += ne * Y * Y;
+      }
+      for (int l = 0; l < L->q; ++l) {
+        const double X = L->xi[l][0] - vx, Y = L->xi[l][1] - vy;
+        const double contr = pxx * X * X + 2.0 * pxy * X * Y + pyy * Y * Y;
+        om[l * plane + c] -= ps / G->tau_g * feq[l] / (r * T * T) * contr;
+      }
+    }
   }
 }
 

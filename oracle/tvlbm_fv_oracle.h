@@ -40,6 +40,8 @@ typedef struct {
   double *dy;                /* spacings after each mesh point (see above)  */
   double emit_lo[ORC_QMAX];  /* feq_l(wall) / sum_out |c.n| feq(wall)       */
   double emit_hi[ORC_QMAX];
+  double tau_g;              /* > 0: the non-unit-Prandtl term of eq.(FINAL) */
+  int pscale;                /* 1: tau -> tau / p, tau_g -> tau_g / p, p = rho T */
 } orc_fv_grid;
 
 /* dy: ny (periodic) or ny-1 (walls) spacings, NULL = all dx.  0 or < 0. */
@@ -47,6 +49,13 @@ int orc_fv_init(const orc_lattice *L, orc_fv_grid *G, int nx, int ny, double dx,
                 const double *dy, double dt, double tau, int collide, int walls,
                 double ulo, double Tlo, double uhi, double Thi);
 void orc_fv_free(orc_fv_grid *G);
+/* Collision of eq.(OMEGAFVLB): tau_g > 0 adds
+ *   -(1/tau_g) feq_l / (rho T^2) Pi : (c_l - u)(c_l - u)
+ * (sign: see the collision term in the .c file),
+ *   Pi_ij = sum_l (f_l - feq_l)(c_l - u)_i (c_l - u)_j   (eq.(FINAL));
+ * tau_g <= 0 leaves single relaxation.  pscale: both relaxation times are
+ * divided by the local pressure p = rho T (Sec. VIII). */
+void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale);
 /* eq.(IMPOSITION) at both wall rows, in place (no-op when periodic) */
 void orc_fv_impose(const orc_lattice *L, const orc_fv_grid *G, double *f);
 /* f = feq(fields) + noise (noise may be NULL), then imposed */

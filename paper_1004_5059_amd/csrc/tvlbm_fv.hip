@@ -21,23 +21,20 @@
 
 namespace tvlbm {
 
+// W = tau Omega of one cell from its deviations d (zero without collisions):
+// single relaxation W_l = feq_l - f_l, then, when set, the non-unit-Prandtl
+// term of eq.(FINAL) and the pressure-rescaled relaxation times (Sec. VIII):
+//   W_l = ps [ (feq_l - f_l) - (tau / tau_g) feq_l Pi:(c_l - u)(c_l - u) / (rho T^2) ],
+//   Pi_ij = sum_l (f_l - feq_l) c_l^i c_l^j  (the central form of eq.(FINAL):
+//   f - feq carries no mass or momentum),  ps = rho T or 1.
+// The term enters with the sign that relaxes Pi at 2 / tau_g, which gives
+// the paper's viscosity c_v rho T tau tau_g / (2 tau + tau_g).
 template <typename R, int N, int ORD, bool COMP>
-__global__ __launch_bounds__(256) void k_fv_omega(const FvArgs<R> A) {
-  constexpr int Q = N * N;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= A.nx || j >= A.ny) return;
+__device__ __forceinline__ void cell_w(const FvArgs<R>& A, const R (&d)[N * N], R (&w)[N * N]) {
   const Lat<R>& L = A.lat;
-  const uint32_t bytes = (uint32_t)(Q * A.plane * (int64_t)sizeof(R));
-  const rsrc_t s = make_rsrc(A.src, bytes);
-  const rsrc_t o = make_rsrc(A.om, bytes);
-  const uint32_t c = (uint32_t)(j * A.ld + i);
-  R d[Q];
-#pragma unroll
-  for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, c, (uint32_t)(l * A.plane));
   if (!A.collide) {
 #pragma unroll
-    for (int l = 0; l < Q; ++l) bst(o, c, (uint32_t)(l * A.plane), R(0));
+    for (int l = 0; l < N * N; ++l) w[l] = R(0);
     return;
   }
   R drho, jx, jy, ed;
@@ -52,11 +49,74 @@ __global__ __launch_bounds__(256) void k_fv_omega(const FvArgs<R> A) {
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const int l = a * N + b;
-      // -(f - feq)/tau in deviations: (w_l e_l - d_l)/tau
-      const R om = fmaR(L.w[l], eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na), -d[l]) * A.inv_tau;
-      bst(o, c, (uint32_t)(l * A.plane), om);
+      w[l] = fmaR(L.w[l], eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na), -d[l]);
     }
   }
+  if (A.tau_ratio == R(0) && !A.pscale) return;
+  const R T = R(1) + F.th;
+  const R ps = A.pscale ? F.rho * T : R(1);
+  if (A.tau_ratio != R(0)) {
+    // S_ij = sum_l (feq_l - f_l) c_i c_j = -Pi_ij
+    R sxx = R(0), sxy = R(0), syy = R(0), cb[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) cb[b] = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      R ra = R(0), rx = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const R v = w[a * N + b];
+        ra += v;
+        rx = fmaR(L.x[b], v, rx);
+        cb[b] += v;
+      }
+      sxx = fmaR(L.x2[a], ra, sxx);
+      sxy = fmaR(L.x[a], rx, sxy);
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) syy = fmaR(L.x2[b], cb[b], syy);
+    const R g = A.tau_ratio / (F.rho * T * T);
+    R cy[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const R Y = L.x[b] - F.uy;
+      cy[b] = syy * Y * Y;
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const R X = L.x[a] - F.ux;
+      const R ax = sxx * X * X, bx = R(2) * sxy * X;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const R Y = L.x[b] - F.uy;
+        const R q = fmaR(bx, Y, ax) + cy[b];  // -Pi:(c - u)(c - u)
+        const R feq = (w[l] + d[l]) + L.w[l];
+        w[l] = ps * fmaR(g * feq, q, w[l]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < N * N; ++l) w[l] *= ps;
+  }
+}
+
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_fv_omega(const FvArgs<R> A) {
+  constexpr int Q = N * N;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= A.nx || j >= A.ny) return;
+  const uint32_t bytes = (uint32_t)(Q * A.plane * (int64_t)sizeof(R));
+  const rsrc_t s = make_rsrc(A.src, bytes);
+  const rsrc_t o = make_rsrc(A.om, bytes);
+  const uint32_t c = (uint32_t)(j * A.ld + i);
+  R d[Q], w[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, c, (uint32_t)(l * A.plane));
+  cell_w<R, N, ORD, COMP>(A, d, w);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) bst(o, c, (uint32_t)(l * A.plane), w[l] * A.inv_tau);
 }
 
 template <typename R, int N>
@@ -318,32 +378,6 @@ __device__ __forceinline__ void store_row(rsrc_t dst, uint32_t c, int64_t plane,
   for (int l = 0; l < N * N; ++l) bst(dst, c, (uint32_t)(l * plane), o[l]);
 }
 
-// W = tau Omega of one row (zero without collisions).
-template <typename R, int N, int ORD, bool COMP>
-__device__ __forceinline__ void row_omega(const Lat<R>& L, bool collide, const R (&d)[N * N],
-                                          R (&w)[N * N]) {
-  if (!collide) {
-#pragma unroll
-    for (int l = 0; l < N * N; ++l) w[l] = R(0);
-    return;
-  }
-  R drho, jx, jy, ed;
-  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
-  const Fields<R> F = fields_from(drho, jx, jy, ed);
-  EqNodes<R, N> E;
-  eq_nodes<R, N, ORD>(L, F, E);
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    R Fa, Ka, Na;
-    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      w[l] = fmaR(L.w[l], eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na), -d[l]);
-    }
-  }
-}
-
 // Per-wavefront constants of the march.  A segment's wavefront marches
 // down (dir = +1) or up (dir = -1) its rows; neighbouring segments march in
 // opposite directions, so the two reads of every halo row fall together and
@@ -502,7 +536,7 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   for (int k = 0; k < ng; ++k, r += C.dir) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
-    row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+    cell_w<R, N, ORD, COMP>(A, d, w);
     row_general<R, N>(A, C, r, d, w, P, pre);
   }
   if (!nst) return;
@@ -515,19 +549,19 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
       load_row<R, N>(C.s, C.cell(r + C.dir), A.plane, bb);
       {
         R w[Q];
-        row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
+        cell_w<R, N, ORD, COMP>(A, ba, w);
         row_steady<R, N>(A, C, r, ba, w, P, pre);
       }
       if (k + 2 < nst) load_row<R, N>(C.s, C.cell(r + 2 * C.dir), A.plane, ba);
       {
         R w[Q];
-        row_omega<R, N, ORD, COMP>(L, A.collide, bb, w);
+        cell_w<R, N, ORD, COMP>(A, bb, w);
         row_steady<R, N>(A, C, r + C.dir, bb, w, P, pre);
       }
     }
     if (k < nst) {
       R w[Q];
-      row_omega<R, N, ORD, COMP>(L, A.collide, ba, w);
+      cell_w<R, N, ORD, COMP>(A, ba, w);
       row_steady<R, N>(A, C, r, ba, w, P, pre);
       r += C.dir;
     }
@@ -535,7 +569,7 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
     for (int k = 0; k < nst; ++k, r += C.dir) {
       R d[Q], w[Q];
       load_row<R, N>(C.s, C.cell(r), A.plane, d);
-      row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+      cell_w<R, N, ORD, COMP>(A, d, w);
       row_steady<R, N>(A, C, r, d, w, P, pre);
     }
   }
@@ -543,7 +577,7 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   for (; r != C.last + C.dir; r += C.dir) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
-    row_omega<R, N, ORD, COMP>(L, A.collide, d, w);
+    cell_w<R, N, ORD, COMP>(A, d, w);
     row_general<R, N>(A, C, r, d, w, P, pre);
   }
 }

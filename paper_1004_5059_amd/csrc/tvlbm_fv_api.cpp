@@ -36,6 +36,8 @@ struct tvlbm_fv {
   FvArgs<float> af{};
   FvArgs<double> ad{};
   tvlbm_fv_schedule sched{1, 6, 0};
+  double tau_g = 0.0;  // > 0: non-unit-Prandtl term
+  int pscale = 0;      // relaxation times divided by the local pressure
 };
 
 namespace {
@@ -86,6 +88,8 @@ void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
   A.segs = (v->d.ny + A.seg_rows - 1) / A.seg_rows;
   A.prefetch = v->sched.prefetch;
   A.wtab = (const double*)v->d_wtab;
+  A.tau_ratio = (v->d.collide && v->tau_g > 0.0) ? (R)(v->d.tau / v->tau_g) : R(0);
+  A.pscale = v->d.collide ? v->pscale : 0;
   if (A.walls) {
     wall_constants<R>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, A.kap_lo, A.phi_lo);
     wall_constants<R>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, A.kap_hi, A.phi_hi);
@@ -319,6 +323,15 @@ int tvlbm_fv_set_schedule(tvlbm_fv* v, const tvlbm_fv_schedule* s) {
   v->sched.fused = s->fused;
   v->sched.prefetch = s->prefetch;
   if (s->seg_rows) v->sched.seg_rows = s->seg_rows;
+  fill_args(v, v->af);
+  fill_args(v, v->ad);
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_set_prandtl(tvlbm_fv* v, double tau_g, int32_t pressure_scaled) {
+  if (!v || std::isnan(tau_g) || (pressure_scaled != 0 && pressure_scaled != 1)) return TVLBM_EINVAL;
+  v->tau_g = (tau_g > 0.0 && std::isfinite(tau_g)) ? tau_g : 0.0;
+  v->pscale = pressure_scaled;
   fill_args(v, v->af);
   fill_args(v, v->ad);
   return TVLBM_OK;

@@ -29,6 +29,8 @@ struct FvArgs {
   int32_t seg_rows;
   int32_t prefetch;     // load row r+1 while row r is processed
   const double* wtab;   // FP64 kap_lo, phi_lo, kap_hi, phi_hi [4][QMAX] (device)
+  R tau_ratio;          // tau / tau_g of the non-unit-Prandtl term, 0 = off
+  int32_t pscale;       // 1: relaxation times divided by the local pressure
 };
 
 // FV_OMEGA + FV_UPDATE: the two-pass step; FV_MARCH: the fused one-pass step

@@ -178,6 +178,7 @@ def lib():
         "tvlbm_fv_step_count": [_vp, _i64p],
         "tvlbm_fv_set_schedule": [_vp, ctypes.c_void_p],
         "tvlbm_fv_get_schedule": [_vp, ctypes.c_void_p],
+        "tvlbm_fv_set_prandtl": [_vp, ctypes.c_double, ctypes.c_int32],
         "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
@@ -764,6 +765,10 @@ def tvlbm_fv_get_schedule(h) -> dict:
     return {"fused": s.fused, "seg_rows": s.seg_rows, "prefetch": s.prefetch}
 
 
+def tvlbm_fv_set_prandtl(h, tau_g: float, pressure_scaled: bool = False):
+    _check(lib().tvlbm_fv_set_prandtl(h, float(tau_g), int(pressure_scaled)))
+
+
 def tvlbm_fv_step_count(h) -> int:
     k = ctypes.c_int64()
     _check(lib().tvlbm_fv_step_count(h, ctypes.byref(k)))
@@ -858,3 +863,9 @@ class FVSolver:
 
     def schedule(self) -> dict:
         return tvlbm_fv_get_schedule(self.h)
+
+    def set_prandtl(self, tau_g: float, pressure_scaled: bool = False):
+        """Non-unit Prandtl number (eq.(FINAL)): tau_g > 0 adds the Pi term,
+        0 removes it; pressure_scaled divides both relaxation times by the
+        local pressure rho T."""
+        tvlbm_fv_set_prandtl(self.h, tau_g, pressure_scaled)

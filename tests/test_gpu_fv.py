@@ -219,3 +219,48 @@ def test_refined_couette_reaches_the_stationary_profile():
           f"mass drift {drift:.2e}")
     assert drift <= 5e-4
     s.close()
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("n,dtype,tol,walls,pscale", [
+    (4, "f64", 1e-12, False, False), (4, "f32", 1e-5, False, True), (4, "f64", 1e-12, True, True),
+    (6, "f64", 1e-12, True, False), (6, "f32", 1e-5, False, False)])
+def test_prandtl_term_parity(n, dtype, tol, walls, pscale, sched):
+    """eq.(FINAL) with tau_g = 0.1 (tau = 0.2, Pr = 1/5), with and without the
+    pressure-rescaled relaxation times, against the oracle."""
+    nx, ny = 40, 26
+    dy = np.random.default_rng(5).uniform(0.7, 1.3, ny - 1 if walls else ny)
+    s = FVSolver(nx, ny, n_gh=n, dtype=dtype, dx=1.0, dt=DT, tau=TAU, dy=dy, walls=walls,
+                 wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1))
+    s.set_schedule(**sched)
+    s.set_prandtl(0.1, pscale)
+    g = orc.OracleFVGrid(orc.OracleLattice(n, LATTICE_ORDER[n]), nx, ny, dx=1.0, dt=DT, tau=TAU,
+                         dy=dy, walls=walls, wall_lo=(0.0, 1.0), wall_hi=(0.04, 1.1), tau_g=0.1,
+                         pscale=pscale)
+    fields, noise = _inputs(nx, ny, n * n, seed=17)
+    fields = (1.2 * fields[0], fields[1], fields[2], 1.1 * fields[3])  # p = rho T away from 1
+    _check(s, g, 60, tol, fields, noise)
+    s.set_prandtl(0.0)  # back to single relaxation
+    s.step(5)
+    assert np.isfinite(to_np(s.populations())).all()
+    s.close()
+
+
+def test_prandtl_shear_viscosity_on_the_gpu():
+    """The viscosity ratio of the oracle pin, measured on the product path
+    (FP32 fused march): nu(tau_g = 0.1) / nu = tau_g / (2 tau + tau_g) = 1/5."""
+    ny, k = 64, 2 * np.pi / 64
+    rates = []
+    for tau_g in (0.0, 0.1):
+        s = FVSolver(2, ny, n_gh=4, dtype="f32", dx=1.0, dt=0.005, tau=0.2)
+        s.set_prandtl(tau_g)
+        y = np.arange(ny)[:, None] * np.ones((1, 2))
+        ux = 0.01 * np.sin(k * y)
+        s.set_fields(1.0, ux, 0 * ux, 1.0)
+        sn = np.sin(k * np.arange(ny))
+        a0 = np.sum(to_np(s.moments()[0])[1][:, 0] * sn)
+        s.step(20000)
+        a1 = np.sum(to_np(s.moments()[0])[1][:, 0] * sn)
+        rates.append(-np.log(a1 / a0) / 100.0)
+        s.close()
+    assert abs(rates[1] / rates[0] / 0.2 - 1) <= 0.01

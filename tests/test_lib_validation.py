@@ -206,3 +206,7 @@ def test_fv_schedule_rejects_null_handles():
     assert T.lib().tvlbm_fv_set_schedule(None, ctypes.byref(s)) == T.TVLBM_EINVAL
     assert T.lib().tvlbm_fv_get_schedule(None, ctypes.byref(s)) == T.TVLBM_EINVAL
     assert ctypes.sizeof(T.tvlbm_fv_schedule) == 12
+
+
+def test_fv_prandtl_rejects_null_handles():
+    assert T.lib().tvlbm_fv_set_prandtl(None, 0.1, 0) == T.TVLBM_EINVAL
