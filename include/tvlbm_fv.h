@@ -105,6 +105,25 @@ int tvlbm_fv_set_schedule(tvlbm_fv *fv, const tvlbm_fv_schedule *s);
  * p = rho T.  No effect without collisions.  Applies to later steps.
  * EINVAL on a null handle, NaN or a flag other than 0 / 1. */
 int tvlbm_fv_set_prandtl(tvlbm_fv *fv, double tau_g, int32_t pressure_scaled);
+
+/* Wall model of the wall rows (no effect when periodic in y).
+ * TVLBM_FV_WALL_DIFFUSE (default): eq.(IMPOSITION) with the fixed wall
+ *   equilibrium (wall_*_ux, wall_*_T of the descriptor); the flow slips and
+ *   the temperature jumps at the wall by amounts of order tau.
+ * TVLBM_FV_WALL_SLIP_FREE: Sec. VII / Appendix B: at every wall point and
+ *   step the wall equilibrium (u_eq, T_eq) is solved for, so that after the
+ *   flux-weighted re-emission the point's own x velocity and temperature
+ *   are the descriptor's wall values.  Newton's method on Appendix B's two
+ *   conditions (its derivatives plus the change of the point's density with
+ *   the emitted populations, which the printed ones leave out), in FP64:
+ *   6 iterations from the wall values after set_fields or a change
+ *   of model, then 3 from each point's root of the previous step, kept on the
+ *   device); one extra launch per step.
+ * Applies to later steps and to tvlbm_fv_set_fields.  EINVAL on a null
+ * handle or another value. */
+#define TVLBM_FV_WALL_DIFFUSE 0
+#define TVLBM_FV_WALL_SLIP_FREE 1
+int tvlbm_fv_set_wall_model(tvlbm_fv *fv, int32_t model);
 int tvlbm_fv_get_schedule(const tvlbm_fv *fv, tvlbm_fv_schedule *s);
 
 #ifdef __cplusplus

@@ -142,6 +142,8 @@ def lib():
         _lib.orc_fv_totals.restype = None
         _lib.orc_fv_set_prandtl.argtypes = [FG, ctypes.c_double, ctypes.c_int]
         _lib.orc_fv_set_prandtl.restype = None
+        _lib.orc_fv_set_wall_model.argtypes = [FG, ctypes.c_int]
+        _lib.orc_fv_set_wall_model.restype = None
     return _lib
 
 
@@ -292,6 +294,8 @@ class FVGrid(ctypes.Structure):
         ("emit_hi", ctypes.c_double * QMAX),
         ("tau_g", ctypes.c_double),
         ("pscale", ctypes.c_int),
+        ("slip_free", ctypes.c_int),
+        ("nr_last", ctypes.c_int),
     ]
 
 
@@ -301,7 +305,7 @@ class OracleFVGrid:
 
     def __init__(self, lat: OracleLattice, nx: int, ny: int, dx: float, dt: float, tau: float,
                  dy=None, collide=True, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0),
-                 tau_g: float = 0.0, pscale: bool = False):
+                 tau_g: float = 0.0, pscale: bool = False, slip_free: bool = False):
         self.lat = lat
         self.nx, self.ny = nx, ny
         self.g = FVGrid()
@@ -314,6 +318,7 @@ class OracleFVGrid:
             raise ValueError("invalid finite-volume mesh")
         self.dual = np.array([lib().orc_fv_dual(ctypes.byref(self.g), j) for j in range(ny)])
         lib().orc_fv_set_prandtl(ctypes.byref(self.g), float(tau_g), int(pscale))
+        lib().orc_fv_set_wall_model(ctypes.byref(self.g), int(slip_free))
 
     def __del__(self):
         try:

@@ -52,6 +52,8 @@ void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale) {
   G->pscale = pscale;
 }
 
+void orc_fv_set_wall_model(orc_fv_grid *G, int slip_free) { G->slip_free = slip_free; }
+
 void orc_fv_free(orc_fv_grid *G) {
   free(G->dy);
   G->dy = NULL;
@@ -79,13 +81,109 @@ static void impose_point(const orc_lattice *L, const orc_fv_grid *G, double *f, 
   }
 }
 
+/* Slip-free re-emission at one wall point (Appendix B).  Unknowns: the wall
+ * equilibrium (ue, Te), started from the prescribed (uw, Tw).  With m the
+ * incoming flux and Z(ue, Te) = sum_out |c.n| feq, the outgoing populations
+ * are (m / Z) feq(ue, Te); the point then has
+ *   F1 = rho uw - sum_l f_l c_x,   F2 = 2 rho Tw + rho uw^2 - sum_l f_l c^2.
+ * Corrections: (Z / m) J^-1 (F1, F2) with J = [[A', B'], [C', D']], where
+ * A..D are the flux-normalised derivatives printed in Appendix B and the
+ * primes add the change of the point's density rho with the emitted
+ * populations, A' = A - uw R_u, C' = C - (2 Tw + uw^2) R_u (R_u like A with
+ * c_x replaced by 1; likewise B', D' with R_T): that is Newton's method on
+ * the same F1, F2 (the printed coefficients omit the rho terms, which with
+ * the flux-weighted emission makes the iteration oscillate and converge only
+ * linearly).  Derivatives of feq by central differences.  Iterated until the
+ * correction is below 1e-15 (at most 50 times); returns the count. */
+static int impose_point_nr(const orc_lattice *L, double *f, long plane, long o, int top, double uw,
+                           double Tw) {
+  const int q = L->q;
+  double cn[ORC_QMAX];
+  double m = 0.0, rin = 0.0, jin = 0.0, ein = 0.0;
+  for (int l = 0; l < q; ++l) {
+    cn[l] = top ? -L->xi[l][1] : L->xi[l][1];
+    if (cn[l] <= 0.0) {
+      const double fl = f[l * plane + o];
+      const double c2 = L->xi[l][0] * L->xi[l][0] + L->xi[l][1] * L->xi[l][1];
+      m += -cn[l] * fl;
+      rin += fl;
+      jin += fl * L->xi[l][0];
+      ein += fl * c2;
+    }
+  }
+  double ue = uw, Te = Tw, fe[ORC_QMAX];
+  int it = 0;
+  while (it < 50) {
+    const double h = 1e-6;
+    double fu1[ORC_QMAX], fu0[ORC_QMAX], fT1[ORC_QMAX], fT0[ORC_QMAX];
+    orc_feq(L, 1.0, ue, 0.0, Te, fe);
+    orc_feq(L, 1.0, ue + h, 0.0, Te, fu1);
+    orc_feq(L, 1.0, ue - h, 0.0, Te, fu0);
+    orc_feq(L, 1.0, ue, 0.0, Te + h, fT1);
+    orc_feq(L, 1.0, ue, 0.0, Te - h, fT0);
+    double Z = 0.0, So = 0.0, Sx = 0.0, S2 = 0.0;
+    double Zu = 0.0, Zt = 0.0, Ou = 0.0, Ot = 0.0, Xu = 0.0, Xt = 0.0, Eu = 0.0, Et = 0.0;
+    for (int l = 0; l < q; ++l) {
+      if (cn[l] <= 0.0) continue;
+      const double cx = L->xi[l][0];
+      const double c2 = cx * cx + L->xi[l][1] * L->xi[l][1];
+      const double du = (fu1[l] - fu0[l]) / (2.0 * h), dT = (fT1[l] - fT0[l]) / (2.0 * h);
+      Z += cn[l] * fe[l];
+      So += fe[l];
+      Sx += cx * fe[l];
+      S2 += c2 * fe[l];
+      Zu += cn[l] * du;
+      Zt += cn[l] * dT;
+      Ou += du;
+      Ot += dT;
+      Xu += cx * du;
+      Xt += cx * dT;
+      Eu += c2 * du;
+      Et += c2 * dT;
+    }
+    const double s = m / Z;
+    const double rho = rin + s * So, jx = jin + s * Sx, e2 = ein + s * S2;
+    const double F1 = rho * uw - jx;
+    const double F2 = 2.0 * rho * Tw + rho * uw * uw - e2;
+    /* Appendix B's coefficients and the density terms */
+    const double A = Xu - Zu * Sx / Z, B = Xt - Zt * Sx / Z;
+    const double C = Eu - Zu * S2 / Z, D = Et - Zt * S2 / Z;
+    const double Ru = Ou - Zu * So / Z, Rt = Ot - Zt * So / Z;
+    const double w2 = 2.0 * Tw + uw * uw;
+    const double A1 = A - uw * Ru, B1 = B - uw * Rt, C1 = C - w2 * Ru, D1 = D - w2 * Rt;
+    const double k = Z / ((A1 * D1 - B1 * C1) * m);
+    const double dU = k * (D1 * F1 - B1 * F2), dT = k * (-C1 * F1 + A1 * F2);
+    ue += dU;
+    Te += dT;
+    ++it;
+    if (fabs(dU) + fabs(dT) < 1e-15) break;
+  }
+  orc_feq(L, 1.0, ue, 0.0, Te, fe);
+  double Z = 0.0;
+  for (int l = 0; l < q; ++l)
+    if (cn[l] > 0.0) Z += cn[l] * fe[l];
+  for (int l = 0; l < q; ++l)
+    if (cn[l] > 0.0) f[l * plane + o] = m / Z * fe[l];
+  return it;
+}
+
 void orc_fv_impose(const orc_lattice *L, const orc_fv_grid *G, double *f) {
   if (!G->walls) return;
   const long plane = (long)G->nx * G->ny;
+  int itmax = 0;
   for (int i = 0; i < G->nx; ++i) {
-    impose_point(L, G, f, plane, i, 0);
-    impose_point(L, G, f, plane, (long)(G->ny - 1) * G->nx + i, 1);
+    const long olo = i, ohi = (long)(G->ny - 1) * G->nx + i;
+    if (G->slip_free) {
+      const int a = impose_point_nr(L, f, plane, olo, 0, G->ulo, G->Tlo);
+      const int b = impose_point_nr(L, f, plane, ohi, 1, G->uhi, G->Thi);
+      if (a > itmax) itmax = a;
+      if (b > itmax) itmax = b;
+    } else {
+      impose_point(L, G, f, plane, olo, 0);
+      impose_point(L, G, f, plane, ohi, 1);
+    }
   }
+  ((orc_fv_grid *)G)->nr_last = itmax;
 }
 
 void orc_fv_set_fields(const orc_lattice *L, const orc_fv_grid *G, const double *rho,

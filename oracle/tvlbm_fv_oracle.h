@@ -42,6 +42,8 @@ typedef struct {
   double emit_hi[ORC_QMAX];
   double tau_g;              /* > 0: the non-unit-Prandtl term of eq.(FINAL) */
   int pscale;                /* 1: tau -> tau / p, tau_g -> tau_g / p, p = rho T */
+  int slip_free;             /* 1: wall equilibria from Newton-Raphson (App. B) */
+  int nr_last;               /* iterations of the last wall-node solve          */
 } orc_fv_grid;
 
 /* dy: ny (periodic) or ny-1 (walls) spacings, NULL = all dx.  0 or < 0. */
@@ -56,6 +58,13 @@ void orc_fv_free(orc_fv_grid *G);
  * tau_g <= 0 leaves single relaxation.  pscale: both relaxation times are
  * divided by the local pressure p = rho T (Sec. VIII). */
 void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale);
+/* Wall model.  0: eq.(IMPOSITION) with the fixed wall equilibrium (ulo, Tlo)
+ * / (uhi, Thi).  1: slip-free walls, eq.(IMPOSITION2) read with the flux
+ * weights of eq.(IMPOSITION): at every wall point and step the wall
+ * equilibrium (u_eq, T_eq) is found by the Newton-Raphson iteration of
+ * Appendix B so that after re-emission the point's own x velocity and
+ * temperature are the prescribed wall values (F1 = F2 = 0). */
+void orc_fv_set_wall_model(orc_fv_grid *G, int slip_free);
 /* eq.(IMPOSITION) at both wall rows, in place (no-op when periodic) */
 void orc_fv_impose(const orc_lattice *L, const orc_fv_grid *G, double *f);
 /* f = feq(fields) + noise (noise may be NULL), then imposed */

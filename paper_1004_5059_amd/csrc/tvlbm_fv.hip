@@ -15,7 +15,11 @@
 //     c . grad d) with the 3 x 3 stencils reading d and Omega through the
 //     caches.
 // At wall points the incoming populations use the one-sided stencils and
-// the outgoing ones are re-emitted from the new incoming normal flux.
+// the outgoing ones are re-emitted from the new incoming normal flux with
+// the fixed wall equilibrium, eq.(IMPOSITION); with slip-free walls
+// k_fv_impose then re-emits them again with the Newton-iterated wall
+// equilibrium (kept out of the step kernels, whose registers it would
+// inflate).
 #include "tvlbm_core.h"
 #include "tvlbm_fv_launch.h"
 
@@ -119,7 +123,137 @@ __global__ __launch_bounds__(256) void k_fv_omega(const FvArgs<R> A) {
   for (int l = 0; l < Q; ++l) bst(o, c, (uint32_t)(l * A.plane), w[l] * A.inv_tau);
 }
 
+// eq.(IMPOSITION) at a wall point of the new state (tab: kap then phi of
+// that wall, FP64 in device memory so that they are loaded only here).  The
+// incoming flux and the re-emitted deviations are formed in FP64 and rounded
+// once (FP32 copies of the constant kap, phi would add the same rounding to
+// the wall mass flux every step).
 template <typename R, int N>
+__device__ __forceinline__ void impose(const Lat<R>& L, const double* __restrict__ tab, bool top,
+                                       R* o) {
+  double m = 0.0;
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) {
+    const R cn = top ? -L.x[l % N] : L.x[l % N];
+    if (cn <= R(0)) m = __builtin_fma(-(double)L.xd[l % N] * (top ? -1.0 : 1.0), (double)o[l], m);
+  }
+#pragma unroll
+  for (int l = 0; l < N * N; ++l) {
+    const R cn = top ? -L.x[l % N] : L.x[l % N];
+    if (cn > R(0)) o[l] = (R)__builtin_fma(tab[QMAX + l], m, tab[l]);
+  }
+}
+
+// Outgoing-moment sums of the unit-density wall equilibrium feq(ue, 0, Te)
+// in FP64: Z = sum |c.n| feq, So = sum feq, Sx = sum c_x feq,
+// S2 = sum |c|^2 feq over the outgoing populations.
+template <int N, int ORD>
+__device__ __forceinline__ void wall_sums(const Lat<double>& Ld, const double* wd, bool top,
+                                          double ue, double Te, double (&S)[4]) {
+  Fields<double> F;
+  F.rho = 1.0; F.drho = 0.0; F.ux = ue; F.uy = 0.0; F.th = Te - 1.0;
+  EqNodes<double, N> E;
+  eq_nodes<double, N, ORD>(Ld, F, E);
+  S[0] = S[1] = S[2] = S[3] = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    double Fa, Ka, Na;
+    eq_anode<double, N, ORD>(Ld, E, a, Fa, Ka, Na);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const double cn = top ? -Ld.x[b] : Ld.x[b];
+      if (cn <= 0.0) continue;
+      const double fe = wd[a * N + b] * (1.0 + eq_dev<double, N, ORD>(Ld, E, a, b, Fa, Ka, Na));
+      S[0] = __builtin_fma(cn, fe, S[0]);
+      S[1] += fe;
+      S[2] = __builtin_fma(Ld.x[a], fe, S[2]);
+      S[3] = __builtin_fma(Ld.x2[a] + Ld.x2[b], fe, S[3]);
+    }
+  }
+}
+
+// Slip-free re-emission at a wall point (App. B): the wall equilibrium
+// (ue, Te) that makes the point's own x velocity and temperature, after the
+// outgoing populations are set to (m / Z) feq(ue, Te), the prescribed
+// (uw, Tw):  F1 = rho uw - sum f c_x = 0,  F2 = 2 rho Tw + rho uw^2 - sum f c^2
+// = 0.  Newton's method with Appendix B's flux-normalised derivatives plus
+// the terms of the point's density (which change with the emitted
+// populations), derivatives of the sums by forward differences, all in
+// FP64.  par holds the start (the prescribed values, or last step's root)
+// and receives the root; iters: 6 from the prescribed values, 3 from last
+// step's root (Newton squares a 1e-6 change to round-off in two).  o holds
+// the new deviations; the incoming ones are used, the outgoing ones written.
+template <typename R, int N, int ORD>
+__device__ __forceinline__ void impose_slip_free(const Lat<R>& L, bool top, double uw, double Tw,
+                                                 int iters, double (&par)[2], R* o) {
+  Lat<double> Ld;
+#pragma unroll
+  for (int a = 0; a < N; ++a) { Ld.x[a] = L.xd[a]; Ld.x2[a] = L.xd[a] * L.xd[a]; }
+  double m = 0.0, rin = 0.0, jin = 0.0, ein = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const double cn = top ? -Ld.x[b] : Ld.x[b];
+      if (cn > 0.0) continue;
+      const double f = L.wd[a * N + b] + (double)o[a * N + b];
+      m = __builtin_fma(-cn, f, m);
+      rin += f;
+      jin = __builtin_fma(Ld.x[a], f, jin);
+      ein = __builtin_fma(Ld.x2[a] + Ld.x2[b], f, ein);
+    }
+  const double h = 1e-7, w2 = 2.0 * Tw + uw * uw;
+  double ue = par[0], Te = par[1];
+  for (int it = 0; it < iters; ++it) {
+    double S[4], Su[4], St[4];
+    wall_sums<N, ORD>(Ld, L.wd, top, ue, Te, S);
+    wall_sums<N, ORD>(Ld, L.wd, top, ue + h, Te, Su);
+    wall_sums<N, ORD>(Ld, L.wd, top, ue, Te + h, St);
+    double du[4], dt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      du[k] = (Su[k] - S[k]) / h;
+      dt[k] = (St[k] - S[k]) / h;
+    }
+    const double Z = S[0], s = m / Z;
+    const double rho = rin + s * S[1];
+    const double F1 = rho * uw - (jin + s * S[2]);
+    const double F2 = w2 * rho - (ein + s * S[3]);
+    // d(moment)/dp * Z / m = dS_k/dp - (dZ/dp) S_k / Z, k = density, c_x, c^2
+    const double Ru = du[1] - du[0] * S[1] / Z, Rt = dt[1] - dt[0] * S[1] / Z;
+    const double A = du[2] - du[0] * S[2] / Z - uw * Ru;
+    const double B = dt[2] - dt[0] * S[2] / Z - uw * Rt;
+    const double C = du[3] - du[0] * S[3] / Z - w2 * Ru;
+    const double D = dt[3] - dt[0] * S[3] / Z - w2 * Rt;
+    const double k = Z / ((A * D - B * C) * m);
+    ue += k * (D * F1 - B * F2);
+    Te += k * (A * F2 - C * F1);
+  }
+  par[0] = ue;
+  par[1] = Te;
+  double S[4];
+  wall_sums<N, ORD>(Ld, L.wd, top, ue, Te, S);
+  const double s = m / S[0];
+  Fields<double> F;
+  F.rho = 1.0; F.drho = 0.0; F.ux = ue; F.uy = 0.0; F.th = Te - 1.0;
+  EqNodes<double, N> E;
+  eq_nodes<double, N, ORD>(Ld, F, E);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    double Fa, Ka, Na;
+    eq_anode<double, N, ORD>(Ld, E, a, Fa, Ka, Na);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const double cn = top ? -Ld.x[b] : Ld.x[b];
+      if (cn <= 0.0) continue;
+      const int l = a * N + b;
+      const double fe = L.wd[l] * (1.0 + eq_dev<double, N, ORD>(Ld, E, a, b, Fa, Ka, Na));
+      o[l] = (R)__builtin_fma(s, fe, -L.wd[l]);
+    }
+  }
+}
+
+template <typename R, int N, int ORD>
 __global__ __launch_bounds__(256) void k_fv_update(const FvArgs<R> A) {
   constexpr int Q = N * N;
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -174,13 +308,13 @@ __global__ __launch_bounds__(256) void k_fv_update(const FvArgs<R> A) {
   // inward normal
   const uint32_t r2 = (uint32_t)(whi ? ny - 2 : 1) * ld;
   R out[Q];
-  R m = R(0);  // incoming normal flux of the new deviations
 #pragma unroll
   for (int a = 0; a < N; ++a) {
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const int l = a * N + b;
       const R cn = whi ? -L.x[b] : L.x[b];
+      out[l] = R(0);
       if (cn > R(0)) continue;
       const uint32_t pl = (uint32_t)(l * A.plane);
       const R f0 = bld<R>(s, r0 + i, pl);
@@ -197,46 +331,46 @@ __global__ __launch_bounds__(256) void k_fv_update(const FvArgs<R> A) {
       const R omb = R(9.0 / 16.0) * w0 + R(3.0 / 32.0) * w1 + R(3.0 / 16.0) * w2 +
                     R(3.0 / 32.0) * w3 + R(1.0 / 32.0) * w5 + R(1.0 / 32.0) * w6;
       out[l] = f0 + dt * (omb - (L.x[a] * dfx + L.x[b] * dfy));
-      m = fmaR(-cn, out[l], m);
     }
   }
-  // eq.(IMPOSITION) in deviations: d_l = kap_l + phi_l m for c.n > 0
+  // the outgoing populations: eq.(IMPOSITION) (a slip-free wall replaces
+  // them afterwards, k_fv_impose)
+  impose<R, N>(L, A.wtab + (whi ? 2 * QMAX : 0), whi, out);
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      const R cn = whi ? -L.x[b] : L.x[b];
-      if (cn > R(0)) out[l] = whi ? fmaR(A.phi_hi[l], m, A.kap_hi[l]) : fmaR(A.phi_lo[l], m, A.kap_lo[l]);
-      bst(dst, r0 + i, (uint32_t)(l * A.plane), out[l]);
-    }
-  }
+  for (int l = 0; l < Q; ++l) bst(dst, r0 + i, (uint32_t)(l * A.plane), out[l]);
 }
 
-// eq.(IMPOSITION) in place at both wall rows (state set from fields).
-template <typename R, int N>
+// The wall model in place at both wall rows: after tvlbm_fv_set_fields,
+// and after every step with slip-free walls (the step kernels re-emit with
+// the fixed wall equilibrium; this replaces the outgoing populations).
+template <typename R, int N, int ORD>
 __global__ __launch_bounds__(256) void k_fv_impose(const FvArgs<R> A) {
   constexpr int Q = N * N;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int side = blockIdx.y;  // 0: first row, 1: last row
   if (i >= A.nx || !A.walls) return;
-  const Lat<R>& L = A.lat;
   const bool whi = side == 1;
   const uint32_t bytes = (uint32_t)(Q * A.plane * (int64_t)sizeof(R));
   const rsrc_t s = make_rsrc(A.dst, bytes);
   const uint32_t c = (uint32_t)((whi ? A.ny - 1 : 0) * A.ld + i);
-  R m = R(0);
+  R o[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) {
-    const R cn = whi ? -L.x[l % N] : L.x[l % N];
-    if (cn <= R(0)) m = fmaR(-cn, bld<R>(s, c, (uint32_t)(l * A.plane)), m);
+  for (int l = 0; l < Q; ++l) o[l] = bld<R>(s, c, (uint32_t)(l * A.plane));
+  if (A.slip_free) {
+    double* wp = A.wpar + 2 * ((int64_t)side * A.nx + i);
+    double par[2] = {A.wall_u[side], A.wall_T[side]};
+    if (A.nr_warm) { par[0] = wp[0]; par[1] = wp[1]; }
+    impose_slip_free<R, N, ORD>(A.lat, whi, A.wall_u[side], A.wall_T[side], A.nr_warm ? 3 : 6,
+                                par, o);
+    wp[0] = par[0];
+    wp[1] = par[1];
+  } else {
+    impose<R, N>(A.lat, A.wtab + (whi ? 2 * QMAX : 0), whi, o);
   }
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    const R cn = whi ? -L.x[l % N] : L.x[l % N];
-    if (cn > R(0))
-      bst(s, c, (uint32_t)(l * A.plane),
-          whi ? fmaR(A.phi_hi[l], m, A.kap_hi[l]) : fmaR(A.phi_lo[l], m, A.kap_lo[l]));
+    const R cn = whi ? -A.lat.x[l % N] : A.lat.x[l % N];
+    if (cn > R(0)) bst(s, c, (uint32_t)(l * A.plane), o[l]);
   }
 }
 
@@ -351,27 +485,6 @@ __device__ __forceinline__ void load_row(rsrc_t s, uint32_t c, int64_t plane, R*
   for (int l = 0; l < N * N; ++l) d[l] = bld<R>(s, c, (uint32_t)(l * plane));
 }
 
-// eq.(IMPOSITION) at a wall point of the new state (tab: kap then phi of
-// that wall, FP64 in device memory so that they are loaded only here).  The
-// incoming flux and the re-emitted deviations are formed in FP64 and rounded
-// once (FP32 copies of the constant kap, phi would add the same rounding to
-// the wall mass flux every step).
-template <typename R, int N>
-__device__ __forceinline__ void impose(const Lat<R>& L, const double* __restrict__ tab, bool top,
-                                       R* o) {
-  double m = 0.0;
-#pragma unroll
-  for (int l = 0; l < N * N; ++l) {
-    const R cn = top ? -L.x[l % N] : L.x[l % N];
-    if (cn <= R(0)) m = __builtin_fma(-(double)L.xd[l % N] * (top ? -1.0 : 1.0), (double)o[l], m);
-  }
-#pragma unroll
-  for (int l = 0; l < N * N; ++l) {
-    const R cn = top ? -L.x[l % N] : L.x[l % N];
-    if (cn > R(0)) o[l] = (R)__builtin_fma(tab[QMAX + l], m, tab[l]);
-  }
-}
-
 template <typename R, int N>
 __device__ __forceinline__ void store_row(rsrc_t dst, uint32_t c, int64_t plane, const R* o) {
 #pragma unroll
@@ -442,7 +555,7 @@ __device__ __forceinline__ void row_steady(const FvArgs<R>& A, const MarchC<R>& 
 // bottom and -h a at the top (one-sided difference, eq.(FVLB2)); wall rows
 // are re-emitted, eq.(IMPOSITION), before they are stored.  A wall row that
 // ends the march is finished on arrival.
-template <typename R, int N>
+template <typename R, int N, int ORD>
 __device__ __forceinline__ void row_general(const FvArgs<R>& A, const MarchC<R>& C, int r,
                                             const R (&d)[N * N], const R (&w)[N * N],
                                             R (&P)[N * N], R (&pre)[N * N]) {
@@ -537,7 +650,7 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
     cell_w<R, N, ORD, COMP>(A, d, w);
-    row_general<R, N>(A, C, r, d, w, P, pre);
+    row_general<R, N, ORD>(A, C, r, d, w, P, pre);
   }
   if (!nst) return;
   if constexpr (PF) {
@@ -578,7 +691,7 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
     R d[Q], w[Q];
     load_row<R, N>(C.s, C.cell(r), A.plane, d);
     cell_w<R, N, ORD, COMP>(A, d, w);
-    row_general<R, N>(A, C, r, d, w, P, pre);
+    row_general<R, N, ORD>(A, C, r, d, w, P, pre);
   }
 }
 
@@ -589,9 +702,10 @@ static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* par
   const dim3 g((unsigned)((A.nx + 63) / 64), (unsigned)((A.ny + 3) / 4)), b(256);
   switch (what) {
     case FV_OMEGA: hipLaunchKernelGGL((k_fv_omega<R, N, ORD, COMP>), g, b, 0, st, A); break;
-    case FV_UPDATE: hipLaunchKernelGGL((k_fv_update<R, N>), g, b, 0, st, A); break;
+    case FV_UPDATE: hipLaunchKernelGGL((k_fv_update<R, N, ORD>), g, b, 0, st, A); break;
     case FV_IMPOSE:
-      hipLaunchKernelGGL((k_fv_impose<R, N>), dim3((unsigned)((A.nx + 255) / 256), 2), b, 0, st, A);
+      hipLaunchKernelGGL((k_fv_impose<R, N, ORD>), dim3((unsigned)((A.nx + 255) / 256), 2), b, 0, st,
+                         A);
       break;
     case FV_POPS: hipLaunchKernelGGL((k_fv_pops<R, N>), g, b, 0, st, A, fields); break;
     case FV_MARCH: {

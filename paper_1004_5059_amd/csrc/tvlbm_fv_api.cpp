@@ -38,6 +38,9 @@ struct tvlbm_fv {
   tvlbm_fv_schedule sched{1, 6, 0};
   double tau_g = 0.0;  // > 0: non-unit-Prandtl term
   int pscale = 0;      // relaxation times divided by the local pressure
+  int slip_free = 0;   // wall model: 0 fixed wall equilibrium, 1 Newton-iterated
+  bool nr_cold = true; // the stored wall roots are not valid yet
+  double* d_wpar = nullptr;  // [2][nx][2] last wall-equilibrium roots
 };
 
 namespace {
@@ -90,6 +93,13 @@ void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
   A.wtab = (const double*)v->d_wtab;
   A.tau_ratio = (v->d.collide && v->tau_g > 0.0) ? (R)(v->d.tau / v->tau_g) : R(0);
   A.pscale = v->d.collide ? v->pscale : 0;
+  A.slip_free = v->slip_free;
+  A.wall_u[0] = v->d.wall_lo_ux;
+  A.wall_T[0] = v->d.wall_lo_T;
+  A.wall_u[1] = v->d.wall_hi_ux;
+  A.wall_T[1] = v->d.wall_hi_T;
+  A.wpar = v->d_wpar;
+  A.nr_warm = 0;
   if (A.walls) {
     wall_constants<R>(v->hl, v->d.wall_lo_ux, v->d.wall_lo_T, 0, A.kap_lo, A.phi_lo);
     wall_constants<R>(v->hl, v->d.wall_hi_ux, v->d.wall_hi_T, 1, A.kap_hi, A.phi_hi);
@@ -122,7 +132,20 @@ int launch(tvlbm_fv* v, int what, const void* src, void* dst, void* fields, doub
 }
 
 int run(tvlbm_fv* v, int what, const void* src, void* dst, void* fields = nullptr,
-        double* partials = nullptr) {
+        double* partials = nullptr);
+
+// the wall model on the state in dst; Newton from last step's roots when
+// they are valid
+int impose_walls(tvlbm_fv* v, void* dst) {
+  v->af.nr_warm = v->ad.nr_warm = v->nr_cold ? 0 : 1;
+  const int rc = run(v, FV_IMPOSE, nullptr, dst);
+  v->af.nr_warm = v->ad.nr_warm = 0;
+  if (rc == TVLBM_OK && v->slip_free) v->nr_cold = false;
+  return rc;
+}
+
+int run(tvlbm_fv* v, int what, const void* src, void* dst, void* fields,
+        double* partials) {
   return v->f64 ? launch<double>(v, what, src, dst, fields, partials)
                 : launch<float>(v, what, src, dst, fields, partials);
 }
@@ -197,7 +220,8 @@ int tvlbm_fv_init(const tvlbm_fv_desc* d, tvlbm_fv** out) {
             hipMalloc(&v->d_vol, sizeof(double) * ny) == hipSuccess &&
             hipMalloc(&v->d_part, sizeof(double) * 4 * v->nblocks) == hipSuccess &&
             hipMalloc(&v->d_tot, sizeof(double) * 4) == hipSuccess &&
-            hipMalloc(&v->d_wtab, sizeof(double) * 4 * QMAX) == hipSuccess;
+            hipMalloc(&v->d_wtab, sizeof(double) * 4 * QMAX) == hipSuccess &&
+            hipMalloc(&v->d_wpar, sizeof(double) * 4 * d->nx) == hipSuccess;
   if (ok) {
     if (v->f64) {
       ok = hipMemcpy(v->d_cy, v->cyh.data(), 8 * ny, hipMemcpyHostToDevice) == hipSuccess;
@@ -223,6 +247,7 @@ int tvlbm_fv_destroy(tvlbm_fv* v) {
   hipFree(v->d_part);
   hipFree(v->d_tot);
   hipFree(v->d_wtab);
+  hipFree(v->d_wpar);
   delete v;
   return TVLBM_OK;
 }
@@ -263,7 +288,8 @@ int tvlbm_fv_set_fields(tvlbm_fv* v, const void* rho, const void* ux, const void
   }
   v->cur = 0;
   v->step = 0;
-  return run(v, FV_IMPOSE, nullptr, v->buf[0]);
+  v->nr_cold = true;
+  return impose_walls(v, v->buf[0]);
 }
 
 int tvlbm_fv_step(tvlbm_fv* v, int32_t nsteps) {
@@ -276,6 +302,10 @@ int tvlbm_fv_step(tvlbm_fv* v, int32_t nsteps) {
       int rc = run(v, FV_OMEGA, v->buf[v->cur], nullptr);
       if (rc) return rc;
       rc = run(v, FV_UPDATE, v->buf[v->cur], v->buf[v->cur ^ 1]);
+      if (rc) return rc;
+    }
+    if (v->slip_free && v->d.y_bc == TVLBM_BC_DIFFUSE_WALLS) {
+      const int rc = impose_walls(v, v->buf[v->cur ^ 1]);
       if (rc) return rc;
     }
     v->cur ^= 1;
@@ -332,6 +362,16 @@ int tvlbm_fv_set_prandtl(tvlbm_fv* v, double tau_g, int32_t pressure_scaled) {
   if (!v || std::isnan(tau_g) || (pressure_scaled != 0 && pressure_scaled != 1)) return TVLBM_EINVAL;
   v->tau_g = (tau_g > 0.0 && std::isfinite(tau_g)) ? tau_g : 0.0;
   v->pscale = pressure_scaled;
+  fill_args(v, v->af);
+  fill_args(v, v->ad);
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_set_wall_model(tvlbm_fv* v, int32_t model) {
+  if (!v || (model != TVLBM_FV_WALL_DIFFUSE && model != TVLBM_FV_WALL_SLIP_FREE))
+    return TVLBM_EINVAL;
+  v->slip_free = model == TVLBM_FV_WALL_SLIP_FREE;
+  v->nr_cold = true;
   fill_args(v, v->af);
   fill_args(v, v->ad);
   return TVLBM_OK;

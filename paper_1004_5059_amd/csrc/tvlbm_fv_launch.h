@@ -31,6 +31,10 @@ struct FvArgs {
   const double* wtab;   // FP64 kap_lo, phi_lo, kap_hi, phi_hi [4][QMAX] (device)
   R tau_ratio;          // tau / tau_g of the non-unit-Prandtl term, 0 = off
   int32_t pscale;       // 1: relaxation times divided by the local pressure
+  int32_t slip_free;    // 1: wall equilibria by Newton iteration (App. B)
+  int32_t nr_warm;      // 1: start from the stored roots of the last step
+  double wall_u[2], wall_T[2];  // prescribed wall velocity / temperature (lo, hi)
+  double* wpar;         // [2][nx][2] last (u_eq, T_eq) of every wall point
 };
 
 // FV_OMEGA + FV_UPDATE: the two-pass step; FV_MARCH: the fused one-pass step

@@ -179,6 +179,7 @@ def lib():
         "tvlbm_fv_set_schedule": [_vp, ctypes.c_void_p],
         "tvlbm_fv_get_schedule": [_vp, ctypes.c_void_p],
         "tvlbm_fv_set_prandtl": [_vp, ctypes.c_double, ctypes.c_int32],
+        "tvlbm_fv_set_wall_model": [_vp, ctypes.c_int32],
         "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
@@ -769,6 +770,13 @@ def tvlbm_fv_set_prandtl(h, tau_g: float, pressure_scaled: bool = False):
     _check(lib().tvlbm_fv_set_prandtl(h, float(tau_g), int(pressure_scaled)))
 
 
+TVLBM_FV_WALL_DIFFUSE, TVLBM_FV_WALL_SLIP_FREE = 0, 1
+
+
+def tvlbm_fv_set_wall_model(h, model: int):
+    _check(lib().tvlbm_fv_set_wall_model(h, int(model)))
+
+
 def tvlbm_fv_step_count(h) -> int:
     k = ctypes.c_int64()
     _check(lib().tvlbm_fv_step_count(h, ctypes.byref(k)))
@@ -869,3 +877,9 @@ class FVSolver:
         0 removes it; pressure_scaled divides both relaxation times by the
         local pressure rho T."""
         tvlbm_fv_set_prandtl(self.h, tau_g, pressure_scaled)
+
+    def set_wall_model(self, slip_free: bool):
+        """Diffuse walls with the fixed wall equilibrium (False, default) or
+        slip-free walls (True): the wall equilibrium is Newton-iterated so that
+        the wall points carry the prescribed velocity and temperature."""
+        tvlbm_fv_set_wall_model(self.h, TVLBM_FV_WALL_SLIP_FREE if slip_free else TVLBM_FV_WALL_DIFFUSE)

@@ -210,3 +210,7 @@ def test_fv_schedule_rejects_null_handles():
 
 def test_fv_prandtl_rejects_null_handles():
     assert T.lib().tvlbm_fv_set_prandtl(None, 0.1, 0) == T.TVLBM_EINVAL
+
+
+def test_fv_wall_model_rejects_null_handles():
+    assert T.lib().tvlbm_fv_set_wall_model(None, 1) == T.TVLBM_EINVAL
