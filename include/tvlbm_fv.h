@@ -14,7 +14,7 @@
  *     eq.(IMPOSITION), from the new incoming normal flux;
  *   - the Hermite equilibrium of Sec. II / Appendix A on the same
  *     tensor-product Gauss-Hermite sets as include/tvlbm.h (c_l = xi_l).
- * Periodic in x; periodic in y or walled.
+ * Periodic in x or with zero-gradient ends; periodic in y or walled.
  *
  * Conventions as in include/tvlbm.h: return TVLBM_OK or a negative
  * TVLBM_E* code, TVLBM_F32 / TVLBM_F64, device buffers caller-owned,
@@ -36,7 +36,9 @@ typedef struct tvlbm_fv tvlbm_fv;
 
 typedef struct tvlbm_fv_desc {
   int32_t n_gh;        /* Gauss-Hermite points per axis: 3, 4 or 6          */
-  int32_t eq_order;    /* 2, 3 or 4 (with n_gh 3, 4, 6)                     */
+  int32_t eq_order;    /* 2, 3 or 4 (with n_gh 3, 4, 6), or 5 with n_gh 6   */
+                       /* (Appendix A's fifth order; the 6-point rule      */
+                       /* integrates its moments exactly)                  */
   int32_t dtype;       /* TVLBM_F32 | TVLBM_F64                             */
   int32_t compensated; /* FP32: compensated moment sums (1) or plain (0)    */
   int32_t nx, ny;      /* mesh points; walls need ny >= 3                   */
@@ -124,6 +126,14 @@ int tvlbm_fv_set_prandtl(tvlbm_fv *fv, double tau_g, int32_t pressure_scaled);
 #define TVLBM_FV_WALL_DIFFUSE 0
 #define TVLBM_FV_WALL_SLIP_FREE 1
 int tvlbm_fv_set_wall_model(tvlbm_fv *fv, int32_t model);
+
+/* x ends.  TVLBM_FV_X_PERIODIC (default), or TVLBM_FV_X_ZERO_GRADIENT: the
+ * adiabatic ends of Sec. VI, every population copied across each end
+ * (f(-dx) = f(0) and beyond the last point the last point).  Applies to
+ * later steps.  EINVAL on a null handle or another value. */
+#define TVLBM_FV_X_PERIODIC 0
+#define TVLBM_FV_X_ZERO_GRADIENT 1
+int tvlbm_fv_set_x_ends(tvlbm_fv *fv, int32_t mode);
 int tvlbm_fv_get_schedule(const tvlbm_fv *fv, tvlbm_fv_schedule *s);
 
 #ifdef __cplusplus

@@ -144,6 +144,8 @@ def lib():
         _lib.orc_fv_set_prandtl.restype = None
         _lib.orc_fv_set_wall_model.argtypes = [FG, ctypes.c_int]
         _lib.orc_fv_set_wall_model.restype = None
+        _lib.orc_fv_set_x_ends.argtypes = [FG, ctypes.c_int]
+        _lib.orc_fv_set_x_ends.restype = None
     return _lib
 
 
@@ -295,6 +297,7 @@ class FVGrid(ctypes.Structure):
         ("tau_g", ctypes.c_double),
         ("pscale", ctypes.c_int),
         ("slip_free", ctypes.c_int),
+        ("x_open", ctypes.c_int),
         ("nr_last", ctypes.c_int),
     ]
 
@@ -305,7 +308,8 @@ class OracleFVGrid:
 
     def __init__(self, lat: OracleLattice, nx: int, ny: int, dx: float, dt: float, tau: float,
                  dy=None, collide=True, walls=False, wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0),
-                 tau_g: float = 0.0, pscale: bool = False, slip_free: bool = False):
+                 tau_g: float = 0.0, pscale: bool = False, slip_free: bool = False,
+                 x_open: bool = False):
         self.lat = lat
         self.nx, self.ny = nx, ny
         self.g = FVGrid()
@@ -319,6 +323,7 @@ class OracleFVGrid:
         self.dual = np.array([lib().orc_fv_dual(ctypes.byref(self.g), j) for j in range(ny)])
         lib().orc_fv_set_prandtl(ctypes.byref(self.g), float(tau_g), int(pscale))
         lib().orc_fv_set_wall_model(ctypes.byref(self.g), int(slip_free))
+        lib().orc_fv_set_x_ends(ctypes.byref(self.g), int(x_open))
 
     def __del__(self):
         try:

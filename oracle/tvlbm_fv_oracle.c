@@ -53,6 +53,7 @@ void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale) {
 }
 
 void orc_fv_set_wall_model(orc_fv_grid *G, int slip_free) { G->slip_free = slip_free; }
+void orc_fv_set_x_ends(orc_fv_grid *G, int x_open) { G->x_open = x_open; }
 
 void orc_fv_free(orc_fv_grid *G) {
   free(G->dy);
@@ -247,7 +248,10 @@ void orc_fv_step(const orc_lattice *L, const orc_fv_grid *G, const double *f, do
   for (int j = 0; j < ny; ++j) {
     const int wall_lo = G->walls && j == 0, wall_hi = G->walls && j == ny - 1;
     for (int i = 0; i < nx; ++i) {
-      const int ip = wrapi(i + 1, nx), im = wrapi(i - 1, nx);
+      /* x neighbours: periodic, or the end point itself beyond a
+       * zero-gradient end */
+      const int ip = G->x_open ? (i + 1 < nx ? i + 1 : nx - 1) : wrapi(i + 1, nx);
+      const int im = G->x_open ? (i > 0 ? i - 1 : 0) : wrapi(i - 1, nx);
       for (int l = 0; l < L->q; ++l) {
         const double cx = L->xi[l][0], cy = L->xi[l][1];
         const double *F = f + l * plane, *W = om + l * plane;

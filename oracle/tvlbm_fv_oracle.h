@@ -43,6 +43,8 @@ typedef struct {
   double tau_g;              /* > 0: the non-unit-Prandtl term of eq.(FINAL) */
   int pscale;                /* 1: tau -> tau / p, tau_g -> tau_g / p, p = rho T */
   int slip_free;             /* 1: wall equilibria from Newton-Raphson (App. B) */
+  int x_open;                /* 1: zero-gradient x ends, f(-dx) = f(0),
+                                f(L_x) = f(L_x - dx) (Sec. VI); 0: periodic */
   int nr_last;               /* iterations of the last wall-node solve          */
 } orc_fv_grid;
 
@@ -65,6 +67,8 @@ void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale);
  * Appendix B so that after re-emission the point's own x velocity and
  * temperature are the prescribed wall values (F1 = F2 = 0). */
 void orc_fv_set_wall_model(orc_fv_grid *G, int slip_free);
+/* x ends: 0 periodic, 1 zero gradient (adiabatic) for every population */
+void orc_fv_set_x_ends(orc_fv_grid *G, int x_open);
 /* eq.(IMPOSITION) at both wall rows, in place (no-op when periodic) */
 void orc_fv_impose(const orc_lattice *L, const orc_fv_grid *G, double *f);
 /* f = feq(fields) + noise (noise may be NULL), then imposed */

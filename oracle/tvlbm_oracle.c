@@ -130,7 +130,7 @@ static double snap(double s) {
 }
 
 int orc_lattice_gh(int n, int order, double cfl, int cfl_norm, orc_lattice *L) {
-  if (n < 2 || n > ORC_NMAX || order < 2 || order > 4 || !(cfl > 0.0)) return -1;
+  if (n < 2 || n > ORC_NMAX || order < 2 || order > 5 || !(cfl > 0.0)) return -1;
   memset(L, 0, sizeof *L);
   L->n = n;
   L->q = n * n;
@@ -154,7 +154,7 @@ int orc_lattice_gh(int n, int order, double cfl, int cfl_norm, orc_lattice *L) {
 
 /* ------------------------------------------------------------------------ */
 /* Equilibrium: Hermite expansion of Sec. II written in the scalar form of   */
-/* Appendix A (orders 2, 3, 4).  The density multiplies every order (the    */
+/* Appendix A (orders 2 to 5).  The density multiplies every order (the     */
 /* appendix prints it only in the fifth-order term).                        */
 /*   u_l = u . xi_l,  u2 = |u|^2,  c2 = |xi_l|^2,  th = T - 1                */
 /* ------------------------------------------------------------------------ */
@@ -174,6 +174,12 @@ void orc_feq(const orc_lattice *L, double rho, double ux, double uy, double T,
       sum += (ul * ul * ul * ul - 6.0 * ul * ul * u2 + 3.0 * u2 * u2) / 24.0;
       sum += (th / 4.0) * ((c2 - D - 2.0) * (ul * ul - u2) - 2.0 * ul * ul);
       sum += (th * th / 8.0) * (c2 * c2 - 2.0 * (D + 2.0) * c2 + D * (D + 2.0));
+    }
+    if (L->order >= 5) {
+      const double ul3 = ul * ul * ul;
+      sum += (ul3 * ul * ul - 10.0 * u2 * ul3 + 15.0 * u2 * u2 * ul) / 120.0;
+      sum += (th / 12.0) * (c2 * ul3 - (D + 6.0) * ul3 - 3.0 * c2 * ul * u2 + (3.0 * D + 12.0) * u2 * ul);
+      sum += (th * th / 8.0) * (ul * c2 * c2 - (2.0 * D + 8.0) * c2 * ul + (D * D + 6.0 * D + 8.0) * ul);
     }
     feq[l] = L->w[l] * rho * sum;
   }

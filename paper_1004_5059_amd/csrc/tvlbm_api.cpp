@@ -479,7 +479,7 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
     c->dyh.assign(d->dy, d->dy + d->ny);
     c->rows = true;
   }
-  if (!build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &c->hl))
+  if (d->eq_order > 4 || !build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &c->hl))
     return bad(TVLBM_EUNSUPPORTED, "lattice");
   c->f64 = d->dtype == TVLBM_F64;
   c->comp = c->f64 ? false : (d->compensated != 0);
@@ -1103,7 +1103,10 @@ int tvlbm_batch_init(const tvlbm_batch_desc* d, tvlbm_batch** out) {
   b->d.inst = nullptr;
   for (const auto& I : b->inst)
     if (!(I.tau > 0.5)) { delete b; return TVLBM_EINVAL; }
-  if (!build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &b->hl)) { delete b; return TVLBM_EUNSUPPORTED; }
+  if (d->eq_order > 4 || !build_lattice(d->n_gh, d->eq_order, d->cfl, d->cfl_norm, &b->hl)) {
+    delete b;
+    return TVLBM_EUNSUPPORTED;
+  }
   b->f64 = d->dtype == TVLBM_F64;
   b->comp = b->f64 ? false : (d->compensated != 0);
   b->st = (hipStream_t)d->stream;

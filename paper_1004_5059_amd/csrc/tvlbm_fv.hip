@@ -25,6 +25,47 @@
 
 namespace tvlbm {
 
+// Equilibrium deviations of one cell, e_l = feq_l / w_l - 1 (Sec. II,
+// Appendix A), for every population.  Orders 2-4: the per-node split of the
+// lattice step; order 5: Appendix A term by term (u_l = u . c_l,
+// c^2 = |c_l|^2, D = 2), e_l = drho + rho P_l with P_l the polynomial
+// without its constant 1.
+template <typename R, int N, int ORD>
+__device__ __forceinline__ void eq_devs(const Lat<R>& L, const Fields<R>& F, R (&e)[N * N]) {
+  if constexpr (ORD <= 4) {
+    EqNodes<R, N> E;
+    eq_nodes<R, N, ORD>(L, F, E);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      R Fa, Ka, Na;
+      eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
+#pragma unroll
+      for (int b = 0; b < N; ++b) e[a * N + b] = eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na);
+    }
+  } else {
+    const R U = F.ux, V = F.uy, th = F.th;
+    const R u2 = U * U + V * V, th2 = th * th;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const R ul = fmaR(U, L.x[a], V * L.x[b]);
+        const R c2 = L.x2[a] + L.x2[b];
+        const R ul2 = ul * ul, ul3 = ul2 * ul;
+        R p = ul + R(0.5) * (ul2 - u2 + th * (c2 - R(2)));
+        p += ul * (ul2 - R(3) * u2 + R(3) * th * (c2 - R(4))) * R(1.0 / 6.0);
+        p += (ul2 * ul2 - R(6) * ul2 * u2 + R(3) * u2 * u2) * R(1.0 / 24.0);
+        p += th * ((c2 - R(4)) * (ul2 - u2) - R(2) * ul2) * R(0.25);
+        p += th2 * (c2 * c2 - R(8) * c2 + R(8)) * R(0.125);
+        p += (ul3 * ul2 - R(10) * u2 * ul3 + R(15) * u2 * u2 * ul) * R(1.0 / 120.0);
+        p += th * (c2 * ul3 - R(8) * ul3 - R(3) * c2 * ul * u2 + R(18) * u2 * ul) * R(1.0 / 12.0);
+        p += th2 * ul * (c2 * c2 - R(12) * c2 + R(24)) * R(0.125);
+        e[a * N + b] = fmaR(F.rho, p, F.drho);
+      }
+    }
+  }
+}
+
 // W = tau Omega of one cell from its deviations d (zero without collisions):
 // single relaxation W_l = feq_l - f_l, then, when set, the non-unit-Prandtl
 // term of eq.(FINAL) and the pressure-rescaled relaxation times (Sec. VIII):
@@ -44,18 +85,9 @@ __device__ __forceinline__ void cell_w(const FvArgs<R>& A, const R (&d)[N * N], 
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
-  EqNodes<R, N> E;
-  eq_nodes<R, N, ORD>(L, F, E);
+  eq_devs<R, N, ORD>(L, F, w);
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    R Fa, Ka, Na;
-    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      w[l] = fmaR(L.w[l], eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na), -d[l]);
-    }
-  }
+  for (int l = 0; l < N * N; ++l) w[l] = fmaR(L.w[l], w[l], -d[l]);
   if (A.tau_ratio == R(0) && !A.pscale) return;
   const R T = R(1) + F.th;
   const R ps = A.pscale ? F.rho * T : R(1);
@@ -152,18 +184,16 @@ __device__ __forceinline__ void wall_sums(const Lat<double>& Ld, const double* w
                                           double ue, double Te, double (&S)[4]) {
   Fields<double> F;
   F.rho = 1.0; F.drho = 0.0; F.ux = ue; F.uy = 0.0; F.th = Te - 1.0;
-  EqNodes<double, N> E;
-  eq_nodes<double, N, ORD>(Ld, F, E);
+  double e[N * N];
+  eq_devs<double, N, ORD>(Ld, F, e);
   S[0] = S[1] = S[2] = S[3] = 0.0;
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    double Fa, Ka, Na;
-    eq_anode<double, N, ORD>(Ld, E, a, Fa, Ka, Na);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const double cn = top ? -Ld.x[b] : Ld.x[b];
       if (cn <= 0.0) continue;
-      const double fe = wd[a * N + b] * (1.0 + eq_dev<double, N, ORD>(Ld, E, a, b, Fa, Ka, Na));
+      const double fe = wd[a * N + b] * (1.0 + e[a * N + b]);
       S[0] = __builtin_fma(cn, fe, S[0]);
       S[1] += fe;
       S[2] = __builtin_fma(Ld.x[a], fe, S[2]);
@@ -236,19 +266,16 @@ __device__ __forceinline__ void impose_slip_free(const Lat<R>& L, bool top, doub
   const double s = m / S[0];
   Fields<double> F;
   F.rho = 1.0; F.drho = 0.0; F.ux = ue; F.uy = 0.0; F.th = Te - 1.0;
-  EqNodes<double, N> E;
-  eq_nodes<double, N, ORD>(Ld, F, E);
+  double e[N * N];
+  eq_devs<double, N, ORD>(Ld, F, e);
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    double Fa, Ka, Na;
-    eq_anode<double, N, ORD>(Ld, E, a, Fa, Ka, Na);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const double cn = top ? -Ld.x[b] : Ld.x[b];
       if (cn <= 0.0) continue;
       const int l = a * N + b;
-      const double fe = L.wd[l] * (1.0 + eq_dev<double, N, ORD>(Ld, E, a, b, Fa, Ka, Na));
-      o[l] = (R)__builtin_fma(s, fe, -L.wd[l]);
+      o[l] = (R)__builtin_fma(s, L.wd[l] * (1.0 + e[l]), -L.wd[l]);
     }
   }
 }
@@ -266,7 +293,9 @@ __global__ __launch_bounds__(256) void k_fv_update(const FvArgs<R> A) {
   const rsrc_t om = make_rsrc(A.om, bytes);
   const rsrc_t dst = make_rsrc(A.dst, bytes);
   const uint32_t ld = (uint32_t)A.ld;
-  const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+  // x neighbours: periodic, or the end point itself beyond a zero-gradient end
+  const int ip = i + 1 == nx ? (A.x_open ? nx - 1 : 0) : i + 1;
+  const int im = i == 0 ? (A.x_open ? 0 : nx - 1) : i - 1;
   const bool wlo = A.walls && j == 0, whi = A.walls && j == ny - 1;
   const R dt = A.dt, cxk = A.inv_dx, cyk = A.cy[j];
   const uint32_t r0 = (uint32_t)j * ld;
@@ -616,7 +645,10 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   C.y0 = seg * A.seg_rows;
   C.y1 = min(C.y0 + A.seg_rows, ny);
   const int x0 = strip * 62;
-  C.col = (uint32_t)((x0 - 1 + lane + nx) % nx);
+  // lanes 0 and 63 hold the strip's halo columns: periodic images, or at a
+  // zero-gradient end the end column itself (f(-dx) = f(0))
+  C.col = A.x_open ? (uint32_t)min(max(x0 - 1 + lane, 0), nx - 1)
+                   : (uint32_t)((x0 - 1 + lane + nx) % nx);
   C.out_lane = lane >= 1 && lane <= 62 && x0 - 1 + lane < nx;
   // Scaled row quantities: a8 = 8 a = (d_{i-1} + d_{i+1}) + 6 d and
   // E = e / 8 = c1 (W_{i-1} + W_{i+1}) + c2 W - hx8_a (d_{i+1} - d_{i-1}),
@@ -695,6 +727,31 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   }
 }
 
+// f = feq(rho, u, T) + noise as deviations d = f - w (Sec. II).
+template <typename R, int N, int ORD>
+__global__ __launch_bounds__(256) void k_fv_init(const FvArgs<R> A, const FvInit<R> I) {
+  constexpr int Q = N * N;
+  const int64_t n = (int64_t)A.nx * A.ny;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int j = (int)(c / A.nx), i = (int)(c % A.nx);
+  Fields<R> F;
+  F.rho = I.rho[c];
+  F.drho = F.rho - R(1);
+  F.ux = I.ux[c];
+  F.uy = I.uy[c];
+  F.th = I.T[c] - R(1);
+  R e[Q];
+  eq_devs<R, N, ORD>(A.lat, F, e);
+  const int64_t o = (int64_t)j * A.ld + i;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    R v = A.lat.w[l] * e[l];
+    if (I.noise) v += I.noise[l * n + c];
+    A.dst[o + l * A.plane] = v;
+  }
+}
+
 // ------------------------------------------------------------- dispatch ---
 template <typename R, int N, int ORD, bool COMP>
 static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* partials,
@@ -724,25 +781,43 @@ static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* par
 }
 
 template <typename R, bool COMP>
-static hipError_t fv_lat(int n, int what, const FvArgs<R>& A, R* fields, double* partials,
+static hipError_t fv_lat(int n, int ord, int what, const FvArgs<R>& A, R* fields, double* partials,
                          hipStream_t st) {
-  switch (n) {
-    case 3: return fv_launch<R, 3, 2, COMP>(what, A, fields, partials, st);
-    case 4: return fv_launch<R, 4, 3, COMP>(what, A, fields, partials, st);
-    case 6: return fv_launch<R, 6, 4, COMP>(what, A, fields, partials, st);
-  }
+  if (n == 3 && ord == 2) return fv_launch<R, 3, 2, COMP>(what, A, fields, partials, st);
+  if (n == 4 && ord == 3) return fv_launch<R, 4, 3, COMP>(what, A, fields, partials, st);
+  if (n == 6 && ord == 4) return fv_launch<R, 6, 4, COMP>(what, A, fields, partials, st);
+  if (n == 6 && ord == 5) return fv_launch<R, 6, 5, COMP>(what, A, fields, partials, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fv(int n, bool comp, int what, const FvArgs<float>& A, float* fields,
+hipError_t launch_fv(int n, int ord, bool comp, int what, const FvArgs<float>& A, float* fields,
                      double* partials, hipStream_t st) {
-  return comp ? fv_lat<float, true>(n, what, A, fields, partials, st)
-              : fv_lat<float, false>(n, what, A, fields, partials, st);
+  return comp ? fv_lat<float, true>(n, ord, what, A, fields, partials, st)
+              : fv_lat<float, false>(n, ord, what, A, fields, partials, st);
 }
-hipError_t launch_fv(int n, bool comp, int what, const FvArgs<double>& A, double* fields,
+hipError_t launch_fv(int n, int ord, bool comp, int what, const FvArgs<double>& A, double* fields,
                      double* partials, hipStream_t st) {
   (void)comp;
-  return fv_lat<double, false>(n, what, A, fields, partials, st);
+  return fv_lat<double, false>(n, ord, what, A, fields, partials, st);
+}
+
+template <typename R>
+static hipError_t fv_init(int n, int ord, const FvArgs<R>& A, const FvInit<R>& I, hipStream_t st) {
+  const dim3 g((unsigned)(((int64_t)A.nx * A.ny + 255) / 256)), b(256);
+  if (n == 3 && ord == 2) hipLaunchKernelGGL((k_fv_init<R, 3, 2>), g, b, 0, st, A, I);
+  else if (n == 4 && ord == 3) hipLaunchKernelGGL((k_fv_init<R, 4, 3>), g, b, 0, st, A, I);
+  else if (n == 6 && ord == 4) hipLaunchKernelGGL((k_fv_init<R, 6, 4>), g, b, 0, st, A, I);
+  else if (n == 6 && ord == 5) hipLaunchKernelGGL((k_fv_init<R, 6, 5>), g, b, 0, st, A, I);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_fv_init(int n, int ord, const FvArgs<float>& A, const FvInit<float>& I,
+                          hipStream_t st) {
+  return fv_init(n, ord, A, I, st);
+}
+hipError_t launch_fv_init(int n, int ord, const FvArgs<double>& A, const FvInit<double>& I,
+                          hipStream_t st) {
+  return fv_init(n, ord, A, I, st);
 }
 
 }  // namespace tvlbm

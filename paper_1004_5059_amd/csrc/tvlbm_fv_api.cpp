@@ -39,6 +39,7 @@ struct tvlbm_fv {
   double tau_g = 0.0;  // > 0: non-unit-Prandtl term
   int pscale = 0;      // relaxation times divided by the local pressure
   int slip_free = 0;   // wall model: 0 fixed wall equilibrium, 1 Newton-iterated
+  int x_open = 0;      // x ends: 0 periodic, 1 zero gradient
   bool nr_cold = true; // the stored wall roots are not valid yet
   double* d_wpar = nullptr;  // [2][nx][2] last wall-equilibrium roots
 };
@@ -78,6 +79,7 @@ void fill_args(tvlbm_fv* v, FvArgs<R>& A) {
   A.nx = v->d.nx;
   A.ny = v->d.ny;
   A.walls = v->d.y_bc == TVLBM_BC_DIFFUSE_WALLS;
+  A.x_open = v->x_open;
   A.collide = v->d.collide != 0;
   A.ld = v->ld;
   A.plane = v->plane;
@@ -126,7 +128,7 @@ int launch(tvlbm_fv* v, int what, const void* src, void* dst, void* fields, doub
   A.src = (const R*)src;
   A.dst = (R*)dst;
   A.om = (R*)v->d.omega;
-  return launch_fv(v->hl.n, v->comp, what, A, (R*)fields, partials, v->st) == hipSuccess
+  return launch_fv(v->hl.n, v->hl.order, v->comp, what, A, (R*)fields, partials, v->st) == hipSuccess
              ? TVLBM_OK
              : TVLBM_EHIP;
 }
@@ -255,37 +257,22 @@ int tvlbm_fv_destroy(tvlbm_fv* v) {
 int tvlbm_fv_set_fields(tvlbm_fv* v, const void* rho, const void* ux, const void* uy,
                         const void* T, const void* noise) {
   if (!v || !rho || !ux || !uy || !T) return TVLBM_EINVAL;
-  // f = feq(fields) + noise as deviations (the lattice step's initialiser;
-  // its post-collision output goes to the Omega scratch and is unused)
+  // f = feq(fields) + noise as deviations
+  hipError_t e;
   if (v->f64) {
-    InitArgs<double> A;
-    std::memset(&A, 0, sizeof A);
-    A.lat = v->ad.lat;
-    A.inst.ld = v->ld;
-    A.inst.plane = v->plane;
-    A.inst.nx = v->d.nx;
-    A.inst.ny = v->d.ny;
-    A.rho = (const double*)rho; A.ux = (const double*)ux; A.uy = (const double*)uy;
-    A.T = (const double*)T;
-    A.noise = (const double*)noise;
-    A.f0 = (double*)v->buf[0];
-    A.g0 = (double*)v->d.omega;
-    if (launch_init(v->hl.n, false, A, v->st) != hipSuccess) return TVLBM_EHIP;
+    FvArgs<double> A = v->ad;
+    A.dst = (double*)v->buf[0];
+    const FvInit<double> I{(const double*)rho, (const double*)ux, (const double*)uy,
+                           (const double*)T, (const double*)noise};
+    e = launch_fv_init(v->hl.n, v->hl.order, A, I, v->st);
   } else {
-    InitArgs<float> A;
-    std::memset(&A, 0, sizeof A);
-    A.lat = v->af.lat;
-    A.inst.ld = v->ld;
-    A.inst.plane = v->plane;
-    A.inst.nx = v->d.nx;
-    A.inst.ny = v->d.ny;
-    A.rho = (const float*)rho; A.ux = (const float*)ux; A.uy = (const float*)uy;
-    A.T = (const float*)T;
-    A.noise = (const float*)noise;
-    A.f0 = (float*)v->buf[0];
-    A.g0 = (float*)v->d.omega;
-    if (launch_init(v->hl.n, v->comp, A, v->st) != hipSuccess) return TVLBM_EHIP;
+    FvArgs<float> A = v->af;
+    A.dst = (float*)v->buf[0];
+    const FvInit<float> I{(const float*)rho, (const float*)ux, (const float*)uy, (const float*)T,
+                          (const float*)noise};
+    e = launch_fv_init(v->hl.n, v->hl.order, A, I, v->st);
   }
+  if (e != hipSuccess) return TVLBM_EHIP;
   v->cur = 0;
   v->step = 0;
   v->nr_cold = true;
@@ -372,6 +359,14 @@ int tvlbm_fv_set_wall_model(tvlbm_fv* v, int32_t model) {
     return TVLBM_EINVAL;
   v->slip_free = model == TVLBM_FV_WALL_SLIP_FREE;
   v->nr_cold = true;
+  fill_args(v, v->af);
+  fill_args(v, v->ad);
+  return TVLBM_OK;
+}
+
+int tvlbm_fv_set_x_ends(tvlbm_fv* v, int32_t mode) {
+  if (!v || (mode != TVLBM_FV_X_PERIODIC && mode != TVLBM_FV_X_ZERO_GRADIENT)) return TVLBM_EINVAL;
+  v->x_open = mode == TVLBM_FV_X_ZERO_GRADIENT;
   fill_args(v, v->af);
   fill_args(v, v->ad);
   return TVLBM_OK;

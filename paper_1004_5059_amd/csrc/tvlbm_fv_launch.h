@@ -13,6 +13,7 @@ struct FvArgs {
   Lat<R> lat;           // nodes x_a, x_a^2, weights w_l (FP64 copies for totals)
   int32_t nx, ny;       // mesh points
   int32_t walls;        // 0 periodic in y, 1 wall points at j = 0 and ny-1
+  int32_t x_open;       // 0 periodic in x, 1 zero-gradient x ends
   int32_t collide;      // 0: Omega = 0
   int64_t ld, plane;    // row pitch, ny * ld
   R dt, inv_tau;        // time step, 1/tau
@@ -43,9 +44,21 @@ enum FvKernel { FV_OMEGA = 0, FV_UPDATE = 1, FV_FIELDS = 2, FV_IMPOSE = 3, FV_PO
 
 // FV_FIELDS: fields [4][ny][nx] or null, partials [blocks][4];
 // FV_POPS: fields is the [q][ny][nx] output; FV_IMPOSE acts on A.dst.
-hipError_t launch_fv(int n, bool comp, int what, const FvArgs<float>& A, float* fields,
+// n: Gauss-Hermite points per axis, ord: equilibrium order.
+hipError_t launch_fv(int n, int ord, bool comp, int what, const FvArgs<float>& A, float* fields,
                      double* partials, hipStream_t st);
-hipError_t launch_fv(int n, bool comp, int what, const FvArgs<double>& A, double* fields,
+hipError_t launch_fv(int n, int ord, bool comp, int what, const FvArgs<double>& A, double* fields,
                      double* partials, hipStream_t st);
+
+// f = feq(rho, u, T) + noise into A.dst as deviations (device [ny][nx]
+// fields, noise [q][ny][nx] or null).
+template <typename R>
+struct FvInit {
+  const R *rho, *ux, *uy, *T, *noise;
+};
+hipError_t launch_fv_init(int n, int ord, const FvArgs<float>& A, const FvInit<float>& I,
+                          hipStream_t st);
+hipError_t launch_fv_init(int n, int ord, const FvArgs<double>& A, const FvInit<double>& I,
+                          hipStream_t st);
 
 }  // namespace tvlbm

@@ -73,7 +73,10 @@ bool gauss_hermite_rule(int n, double* x, double* w) {
 }
 
 bool build_lattice(int n, int order, double cfl, int cfl_norm, HostLattice* L) {
-  if (!((n == 3 && order == 2) || (n == 4 && order == 3) || (n == 6 && order == 4))) return false;
+  // order 5 (the 6-point rule integrates H5 H5 exactly) is for the
+  // finite-volume path only; the lattice entry points reject it
+  if (!((n == 3 && order == 2) || (n == 4 && order == 3) || (n == 6 && (order == 4 || order == 5))))
+    return false;
   if (!(cfl > 0.0)) return false;
   *L = HostLattice();
   L->n = n;
@@ -112,6 +115,12 @@ void host_feq(const HostLattice& L, double rho, double ux, double uy, double T, 
       P += (ul2 * ul2 - 6.0 * ul2 * u2 + 3.0 * u2 * u2) / 24.0 +
            th / 4.0 * ((c2 - D - 2.0) * (ul2 - u2) - 2.0 * ul2) +
            th * th / 8.0 * (c2 * c2 - 2.0 * (D + 2.0) * c2 + D * (D + 2.0));
+    if (L.order >= 5) {
+      const double ul3 = ul2 * ul;
+      P += (ul3 * ul2 - 10.0 * u2 * ul3 + 15.0 * u2 * u2 * ul) / 120.0 +
+           th / 12.0 * (c2 * ul3 - (D + 6.0) * ul3 - 3.0 * c2 * ul * u2 + (3.0 * D + 12.0) * u2 * ul) +
+           th * th / 8.0 * (ul * c2 * c2 - (2.0 * D + 8.0) * c2 * ul + (D * D + 6.0 * D + 8.0) * ul);
+    }
     feq[l] = L.w[l] * rho * P;
   }
 }

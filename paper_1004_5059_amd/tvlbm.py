@@ -180,6 +180,7 @@ def lib():
         "tvlbm_fv_get_schedule": [_vp, ctypes.c_void_p],
         "tvlbm_fv_set_prandtl": [_vp, ctypes.c_double, ctypes.c_int32],
         "tvlbm_fv_set_wall_model": [_vp, ctypes.c_int32],
+        "tvlbm_fv_set_x_ends": [_vp, ctypes.c_int32],
         "tvlbm_batch_get_tuning": [_vp, ctypes.c_void_p],
     }
     for name, args in sig.items():
@@ -777,6 +778,13 @@ def tvlbm_fv_set_wall_model(h, model: int):
     _check(lib().tvlbm_fv_set_wall_model(h, int(model)))
 
 
+TVLBM_FV_X_PERIODIC, TVLBM_FV_X_ZERO_GRADIENT = 0, 1
+
+
+def tvlbm_fv_set_x_ends(h, mode: int):
+    _check(lib().tvlbm_fv_set_x_ends(h, int(mode)))
+
+
 def tvlbm_fv_step_count(h) -> int:
     k = ctypes.c_int64()
     _check(lib().tvlbm_fv_step_count(h, ctypes.byref(k)))
@@ -792,7 +800,7 @@ class FVSolver:
     def __init__(self, nx: int, ny: int, n_gh: int = 4, dtype: str = "f32", dx: float = 1.0,
                  dt: float = 0.1, tau: float = 0.8, dy=None, walls: bool = False,
                  wall_lo=(0.0, 1.0), wall_hi=(0.0, 1.0), collide: bool = True,
-                 compensated: bool = True, device=None, stream=None):
+                 compensated: bool = True, device=None, stream=None, eq_order: int | None = None):
         import torch
 
         self.torch = torch
@@ -806,7 +814,7 @@ class FVSolver:
         self.om = torch.zeros(n_el, dtype=self.tdtype, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         d = tvlbm_fv_desc()
-        d.n_gh, d.eq_order = n_gh, LATTICE_ORDER[n_gh]
+        d.n_gh, d.eq_order = n_gh, LATTICE_ORDER[n_gh] if eq_order is None else eq_order
         d.dtype = TVLBM_F32 if dtype == "f32" else TVLBM_F64
         d.compensated = int(compensated)
         d.nx, d.ny, d.ld = nx, ny, self.ld
@@ -883,3 +891,7 @@ class FVSolver:
         slip-free walls (True): the wall equilibrium is Newton-iterated so that
         the wall points carry the prescribed velocity and temperature."""
         tvlbm_fv_set_wall_model(self.h, TVLBM_FV_WALL_SLIP_FREE if slip_free else TVLBM_FV_WALL_DIFFUSE)
+
+    def set_x_ends(self, zero_gradient: bool):
+        """Periodic x (False, default) or zero-gradient (adiabatic) x ends."""
+        tvlbm_fv_set_x_ends(self.h, TVLBM_FV_X_ZERO_GRADIENT if zero_gradient else TVLBM_FV_X_PERIODIC)

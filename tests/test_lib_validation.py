@@ -48,7 +48,7 @@ def test_init_rejects_invalid_descriptors(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(n_gh=5), dict(n_gh=2), dict(n_gh=4, eq_order=5),
-                                dict(n_gh=6, eq_order=2)])
+                                dict(n_gh=6, eq_order=2), dict(n_gh=6, eq_order=5)])
 def test_init_rejects_unsupported_lattices(kw):
     assert _code(T.tvlbm_init, _desc(**kw)) == T.TVLBM_EUNSUPPORTED
 
@@ -214,3 +214,15 @@ def test_fv_prandtl_rejects_null_handles():
 
 def test_fv_wall_model_rejects_null_handles():
     assert T.lib().tvlbm_fv_set_wall_model(None, 1) == T.TVLBM_EINVAL
+
+
+def test_fv_x_ends_reject_null_handles():
+    assert T.lib().tvlbm_fv_set_x_ends(None, 1) == T.TVLBM_EINVAL
+
+
+def test_fifth_order_is_for_the_finite_volume_path_only():
+    """(n_gh 6, order 5) is a valid finite-volume lattice (it passes the
+    lattice check and fails here only for want of a device); the lattice
+    step rejects it (test_init_rejects_unsupported_lattices)."""
+    assert _code(T.tvlbm_fv_init, _fv_desc(n_gh=6, eq_order=5)) != T.TVLBM_EUNSUPPORTED
+    assert _code(T.tvlbm_fv_init, _fv_desc(n_gh=4, eq_order=5)) == T.TVLBM_EUNSUPPORTED
