@@ -81,8 +81,12 @@ int tvlbm_fv_step_count(const tvlbm_fv *fv, int64_t *k);
  * seg_rows rows of a 62-column strip, the 9-point stencils of Sec. III and
  * Sec. VII evaluated in their separable (1-D x 1-D) form.  fused = 0: two
  * passes, Omega of every point into the omega scratch array, then the
- * stencil update.  Both compute the same update; they differ by rounding
- * only (the fused pass sums the stencil terms in another order).
+ * stencil update.  fused = 2 (FP32 with n_gh 3 or 4 only, else
+ * EUNSUPPORTED): one pass with the four wavefronts of a workgroup sharing
+ * a segment of seg_rows rows (rows interleaved, neighbour contributions
+ * exchanged through LDS), for longer segments at the same parallelism.
+ * All compute the same update; they differ by rounding only (the fused
+ * passes sum the stencil terms in another order).
  * seg_rows: 1 .. 65536 rows per wavefront (0 keeps the current value,
  * default 6); prefetch: 1 loads row r+1 while row r is processed (default 0).
  * EINVAL on a null handle or argument, or values out of range. */

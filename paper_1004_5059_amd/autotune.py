@@ -156,32 +156,37 @@ def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: st
 
 
 FV_SEG_ROWS = [4, 5, 6, 7, 8, 10, 12, 16]
+FV_BAND_ROWS = [8, 12, 16, 24, 32, 48, 64]
 
 
 def autotune_fv(solver, steps: int = 20, reps: int = 2):
-    """Fastest schedule of the fused finite-volume step (rows per wavefront
-    segment x row prefetch) for `solver` (an FVSolver; advances its state).
-    Every schedule computes the same update up to rounding order, so the
-    choice only affects speed.  Returns (schedule dict, {label: ms/step})."""
+    """Fastest schedule of the fused finite-volume step for `solver` (an
+    FVSolver; advances its state): the march (rows per wavefront segment x
+    row prefetch) and, for FP32 with q <= 16, the band schedule (rows per
+    workgroup segment).  Every schedule computes the same update up to
+    rounding order, so the choice only affects speed.  Returns (schedule
+    dict, {label: ms/step})."""
     import torch
 
+    cands = [(1, sr, pf) for pf in (False, True) for sr in FV_SEG_ROWS]
+    if solver.tdtype == torch.float32 and solver.q <= 16:
+        cands += [(2, sr, False) for sr in FV_BAND_ROWS]
     times = {}
-    for pf in (False, True):
-        for sr in FV_SEG_ROWS:
-            solver.set_schedule(True, sr, pf)
-            solver.step(2)
-            best = float("inf")
-            for _ in range(reps):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(solver.stream)
-                solver.step(steps)
-                b.record(solver.stream)
-                b.synchronize()
-                best = min(best, a.elapsed_time(b) / steps)
-            times[f"seg{sr}{'_pf' if pf else ''}"] = best
-    label = min(times, key=times.get)
-    sr = int(label[3:].split("_")[0])
-    pf = label.endswith("_pf")
-    solver.set_schedule(True, sr, pf)
-    return solver.schedule(), times
+    for fused, sr, pf in cands:
+        solver.set_schedule(fused, sr, pf)
+        solver.step(2)
+        best = float("inf")
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(solver.stream)
+            solver.step(steps)
+            b.record(solver.stream)
+            b.synchronize()
+            best = min(best, a.elapsed_time(b) / steps)
+        times[(fused, sr, pf)] = best
+    fused, sr, pf = min(times, key=times.get)
+    solver.set_schedule(fused, sr, pf)
+    labels = {f"{'band' if f == 2 else 'seg'}{r}{'_pf' if p else ''}": t
+              for (f, r, p), t in times.items()}
+    return solver.schedule(), labels

@@ -727,6 +727,122 @@ __global__ __launch_bounds__(256) void k_fv_march(const FvArgs<R> A) {
   }
 }
 
+// ------------------------------------------------------------ band march ---
+// The same update with the four wavefronts of a workgroup sharing one row
+// segment of a strip: in band k, wavefront w processes row rs + 4k + w, so
+// a long segment (few halo rows) still gives four wavefronts.  A row r
+// contributes
+//   A_r = d_r + 6 E_r [+- h_r/8 a8_r at a wall row]   (itself),
+//   U_r = b E_r + (h_{r+1}/8) a8_r                     (the row above),
+//   D_r = b E_r - (h_{r-1}/8) a8_r                     (the row below),
+// b = 2 towards a wall row, 1 otherwise, and d'_r = A_r + U_{r-1} + D_{r+1}
+// (the march's partial sums, regrouped).  U and D go through LDS; rows of
+// wavefronts 0-2 finish in their band, wavefront 3's row in the next one
+// (an extra band at the end finishes the last).  FP32 with q <= 16 (the
+// exchange takes 8 q 64 4 bytes = 32 KiB of LDS for D2Q16).
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_fv_band(const FvArgs<R> A) {
+  constexpr int Q = N * N;
+  __shared__ R xs[2][4][Q][64];  // [U, D][wavefront][population][lane]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int strip = t % A.strips, seg = t / A.strips;
+  if (seg >= A.segs) return;  // whole workgroup
+  const Lat<R>& L = A.lat;
+  const int nx = A.nx, ny = A.ny;
+  const uint32_t bytes = (uint32_t)(Q * A.plane * (int64_t)sizeof(R));
+  MarchC<R> C;
+  C.s = make_rsrc(A.src, bytes);
+  C.dst = make_rsrc(A.dst, bytes);
+  C.ld = (uint32_t)A.ld;
+  C.ny = ny;
+  C.walls = A.walls != 0;
+  C.y0 = seg * A.seg_rows;
+  C.y1 = min(C.y0 + A.seg_rows, ny);
+  const int x0 = strip * 62;
+  C.col = A.x_open ? (uint32_t)min(max(x0 - 1 + lane, 0), nx - 1)
+                   : (uint32_t)((x0 - 1 + lane + nx) % nx);
+  C.out_lane = lane >= 1 && lane <= 62 && x0 - 1 + lane < nx;
+  C.c1 = A.dt * A.inv_tau * R(1.0 / 64.0);
+  C.c2 = A.dt * A.inv_tau * R(3.0 / 32.0);
+  C.hx8 = A.dt * A.inv_dx * R(1.0 / 16.0);
+  C.hh8 = A.dt * R(1.0 / 16.0);
+  const int rs = C.walls ? max(C.y0 - 1, 0) : C.y0 - 1;
+  const int re = C.walls ? min(C.y1, ny - 1) : C.y1;
+  C.dir = 1;
+  C.first = rs;
+  C.last = re;
+  const int bands = (re - rs + 1 + 3) / 4 + 1;
+
+  R carry[Q], pend[Q];  // wavefront 0: U of the previous band's last row; 3: its own row
+#pragma unroll
+  for (int l = 0; l < Q; ++l) { carry[l] = R(0); pend[l] = R(0); }
+  int prow = -1;
+  for (int k = 0; k < bands; ++k) {
+    const int r = rs + 4 * k + wave;
+    const bool act = r <= re;
+    R own[Q];
+    if (act) {
+      R d[Q], w[Q];
+      load_row<R, N>(C.s, C.cell(r), A.plane, d);
+      cell_w<R, N, ORD, COMP>(A, d, w);
+      const R hp = C.hh8 * A.cy[C.wrap(r - 1)], hn = C.hh8 * A.cy[C.wrap(r + 1)];
+      const R hc = C.hh8 * A.cy[C.wrap(r)];
+      const R bp = C.wall(r - 1) ? R(2) : R(1), bn = C.wall(r + 1) ? R(2) : R(1);
+      const R kc = (C.walls && r == 0) ? hc : ((C.walls && r == ny - 1) ? -hc : R(0));
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const R hxa = C.hx8 * L.x[a];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          R a8, e;
+          row_quant<R, N>(C, hxa, d[l], w[l], a8, e);
+          own[l] = fmaR(kc * L.x[b], a8, fmaR(R(6), e, d[l]));
+          xs[0][wave][l][lane] = fmaR(hn * L.x[b], a8, bn * e);
+          xs[1][wave][l][lane] = fmaR(-(hp * L.x[b]), a8, bp * e);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        own[l] = R(0);
+        xs[0][wave][l][lane] = R(0);
+        xs[1][wave][l][lane] = R(0);
+      }
+    }
+    __syncthreads();
+    if (wave < 3) {
+      if (act && C.out(r)) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l)
+          own[l] += (wave == 0 ? carry[l] : xs[0][wave - 1][l][lane]) + xs[1][wave + 1][l][lane];
+        if (C.wall(r)) impose<R, N>(L, A.wtab + (r == 0 ? 0 : 2 * QMAX), r != 0, own);
+        if (C.out_lane) store_row<R, N>(C.dst, C.cell(r), A.plane, own);
+      }
+      if (wave == 0) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) carry[l] = xs[0][3][l][lane];
+      }
+    } else {
+      if (prow >= 0 && C.out(prow)) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) pend[l] += xs[1][0][l][lane];
+        if (C.wall(prow)) impose<R, N>(L, A.wtab + (prow == 0 ? 0 : 2 * QMAX), prow != 0, pend);
+        if (C.out_lane) store_row<R, N>(C.dst, C.cell(prow), A.plane, pend);
+      }
+      prow = act ? r : -1;
+      if (act) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) pend[l] = own[l] + xs[0][2][l][lane];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // f = feq(rho, u, T) + noise as deviations d = f - w (Sec. II).
 template <typename R, int N, int ORD>
 __global__ __launch_bounds__(256) void k_fv_init(const FvArgs<R> A, const FvInit<R> I) {
@@ -773,6 +889,16 @@ static hipError_t fv_launch(int what, const FvArgs<R>& A, R* fields, double* par
         hipLaunchKernelGGL((k_fv_march<R, N, ORD, COMP, true>), gm, b, 0, st, A);
       else
         hipLaunchKernelGGL((k_fv_march<R, N, ORD, COMP, false>), gm, b, 0, st, A);
+      break;
+    }
+    case FV_BAND: {
+      if constexpr (sizeof(R) == 4 && N <= 4) {
+        const int tiles = A.strips * A.segs;  // one workgroup per segment
+        hipLaunchKernelGGL((k_fv_band<R, N, ORD, COMP>), dim3((unsigned)((tiles + 7) / 8 * 8)), b, 0, st,
+                           A);
+      } else {
+        return hipErrorInvalidValue;
+      }
       break;
     }
     default: hipLaunchKernelGGL((k_fv_fields<R, N, COMP>), g, b, 0, st, A, fields, partials); break;

@@ -283,7 +283,8 @@ int tvlbm_fv_step(tvlbm_fv* v, int32_t nsteps) {
   if (!v || nsteps < 0) return TVLBM_EINVAL;
   for (int32_t s = 0; s < nsteps; ++s) {
     if (v->sched.fused) {
-      const int rc = run(v, FV_MARCH, v->buf[v->cur], v->buf[v->cur ^ 1]);
+      const int rc = run(v, v->sched.fused == 2 ? FV_BAND : FV_MARCH, v->buf[v->cur],
+                         v->buf[v->cur ^ 1]);
       if (rc) return rc;
     } else {
       int rc = run(v, FV_OMEGA, v->buf[v->cur], nullptr);
@@ -334,7 +335,8 @@ int tvlbm_fv_moments(tvlbm_fv* v, void* rho, void* ux, void* uy, void* T, double
 
 int tvlbm_fv_set_schedule(tvlbm_fv* v, const tvlbm_fv_schedule* s) {
   if (!v || !s) return TVLBM_EINVAL;
-  if ((s->fused != 0 && s->fused != 1) || s->seg_rows < 0 || s->seg_rows > 65536 ||
+  if (s->fused == 2 && (v->f64 || v->hl.n > 4)) return TVLBM_EUNSUPPORTED;
+  if (s->fused < 0 || s->fused > 2 || s->seg_rows < 0 || s->seg_rows > 65536 ||
       (s->prefetch != 0 && s->prefetch != 1))
     return TVLBM_EINVAL;
   v->sched.fused = s->fused;

@@ -39,8 +39,9 @@ struct FvArgs {
 };
 
 // FV_OMEGA + FV_UPDATE: the two-pass step; FV_MARCH: the fused one-pass step
+// FV_BAND: the fused step with four wavefronts per row segment (FP32, q <= 16)
 enum FvKernel { FV_OMEGA = 0, FV_UPDATE = 1, FV_FIELDS = 2, FV_IMPOSE = 3, FV_POPS = 4,
-                FV_MARCH = 5 };
+                FV_MARCH = 5, FV_BAND = 6 };
 
 // FV_FIELDS: fields [4][ny][nx] or null, partials [blocks][4];
 // FV_POPS: fields is the [q][ny][nx] output; FV_IMPOSE acts on A.dst.

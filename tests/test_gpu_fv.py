@@ -388,3 +388,31 @@ def test_sod_shock_tube_of_sec6(t_end, l1_max):
     assert l1 <= l1_max and shock <= 0.01 * (xs - 0.5) and abs(pstar) <= 0.02
     assert abs(t1[0] - t0[0]) / t0[0] <= 1e-12 and abs(t1[3] - t0[3]) / t0[3] <= 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("n", [4, 3])
+@pytest.mark.parametrize("nx,ny,seg_rows,walls,x_open", [
+    (70, 37, 16, False, False), (61, 40, 8, True, False), (125, 33, 1, True, False),
+    (62, 21, 64, False, True), (5, 9, 3, True, True), (124, 3, 4, True, False)])
+def test_band_schedule_parity(n, nx, ny, seg_rows, walls, x_open):
+    """The band schedule (four wavefronts per segment, LDS exchange), FP32,
+    against the oracle: segments of 1 row to longer than the mesh, widths
+    around the strips, walls and zero-gradient ends."""
+    dy = np.random.default_rng(nx * ny).uniform(0.6, 1.4, ny - 1 if walls else ny)
+    s = FVSolver(nx, ny, n_gh=n, dtype="f32", dx=1.0, dt=DT, tau=TAU, dy=dy, walls=walls,
+                 wall_lo=(0.0, 1.0), wall_hi=(0.03, 1.05))
+    s.set_schedule(2, seg_rows, False)
+    s.set_x_ends(x_open)
+    g = orc.OracleFVGrid(orc.OracleLattice(n, LATTICE_ORDER[n]), nx, ny, dx=1.0, dt=DT, tau=TAU,
+                         dy=dy, walls=walls, wall_lo=(0.0, 1.0), wall_hi=(0.03, 1.05),
+                         x_open=x_open)
+    assert s.schedule()["fused"] == 2
+    _check(s, g, 30, 1e-5, *_inputs(nx, ny, n * n, seed=nx + ny))
+    s.close()
+
+
+def test_band_schedule_is_fp32_and_small_lattices_only():
+    s = FVSolver(16, 8, n_gh=6, dtype="f32")
+    with pytest.raises(Exception):
+        s.set_schedule(2, 16, False)
+    s.close()
