@@ -346,6 +346,41 @@ def test_fifth_order_and_zero_gradient_ends_parity(dtype, tol, walls, sched):
         s.close()
 
 
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("n,order", [(4, 3), (6, 5)])
+def test_zero_gradient_ends_exchange_only_the_end_fluxes(n, order, sched):
+    """The balance law of the zero-gradient ends on the GPU path, FP64, at a
+    width of 17 strips where the oracle is not run: on a uniform periodic y
+    mesh each collision invariant phi (1, c_x, c_y, |c|^2 / 2) changes per
+    step by -dt dy sum_j sum_l phi_l c_x (f_l(x_end, y_j) - f_l(x_0, y_j)),
+    with the nodes from the library's own lattice table."""
+    from paper_1004_5059_amd.tvlbm import tvlbm_lattice_table
+
+    nx, ny, dx, dt = 1040, 8, 0.1, 0.004
+    s = FVSolver(nx, ny, n_gh=n, dtype="f64", dx=dx, dt=dt, tau=0.05, dy=np.full(ny, dx),
+                 eq_order=order)
+    s.set_schedule(**sched)
+    s.set_x_ends(True)
+    X, Y = np.meshgrid(np.arange(nx) * dx, np.arange(ny) * dx)
+    L = nx * dx
+    s.set_fields(1 + 0.2 * X / L + 0.05 * np.cos(2 * np.pi * Y / (ny * dx)),
+                 0.1 + 0.1 * X / L, 0.02 + 0.03 * np.sin(2 * np.pi * Y / (ny * dx)) + 0.02 * X / L,
+                 1 + 0.1 * X / L)
+    xi = tvlbm_lattice_table(n, order)[0]
+    cx, cy = xi[:, 0], xi[:, 1]
+    phi = np.stack([np.ones_like(cx), cx, cy, 0.5 * (cx * cx + cy * cy)])
+    for _ in range(3):
+        f = to_np(s.populations())
+        _, t0 = s.moments()
+        want = -dt * dx * (phi * cx) @ np.sum(f[:, :, -1] - f[:, :, 0], axis=1)
+        s.step(1)
+        _, t1 = s.moments()
+        got = np.asarray(t1) - np.asarray(t0)
+        assert np.all(np.abs(want) > 1e-6)
+        assert np.allclose(got, want, rtol=1e-9, atol=1e-13 * np.abs(t0).max()), (got, want)
+    s.close()
+
+
 @pytest.mark.parametrize("t_end,l1_max", [(0.1, 0.02), (0.2, 0.025)])
 def test_sod_shock_tube_of_sec6(t_end, l1_max):
     """The shock tube of Sec. VI at its own resolution: L_x = 1 with 1500 x 2
@@ -357,7 +392,7 @@ def test_sod_shock_tube_of_sec6(t_end, l1_max):
     within the L1 error the finite viscosity and conductivity leave (the
     contact and the rarefaction ends are smoothed), the shock position
     within 1 % of its travel, the star pressure within 2 %, mass and energy
-    conserved."""
+    conserved while no population has reached the ends."""
     import sod_exact as se
 
     nx, dx = 1500, 1.0 / 1500
@@ -386,7 +421,12 @@ def test_sod_shock_tube_of_sec6(t_end, l1_max):
     print(f"Sod t={t_end}: L1 rho {l1:.4f}, shock offset {shock / dx:.1f} points, "
           f"star p {pstar:+.4f}")
     assert l1 <= l1_max and shock <= 0.01 * (xs - 0.5) and abs(pstar) <= 0.02
-    assert abs(t1[0] - t0[0]) / t0[0] <= 1e-12 and abs(t1[3] - t0[3]) / t0[3] <= 1e-12
+    # the fastest D2Q36 population (|c| = 3.32 at T = 1) reaches the ends at
+    # t = 0.15; from then on the ends exchange mass and energy (their
+    # balance law is the end-flux test above), at 1e-9 of the totals by
+    # t = 0.2, as the oracle shows on a 300-point tube
+    cons = 1e-12 if t_end * 3.33 < 0.5 else 1e-8
+    assert abs(t1[0] - t0[0]) / t0[0] <= cons and abs(t1[3] - t0[3]) / t0[3] <= cons
     s.close()
 
 
