@@ -28,6 +28,8 @@ struct Variant {
   int prefetch;  // software-pipelined rows
   int pairs;     // FP32 step on two adjacent columns per lane (8-byte accesses);
                  // grids it does not apply to run the same shape one column per lane
+  int two;       // two steps per launch (k_march2, rows = output rows per segment)
+                 // where it applies; single steps and other grids run variant 0
 };
 // Launch shapes of the fused step; all compute identical results.  Variant
 // 0 is the default.
@@ -35,7 +37,8 @@ const Variant kVariants[] = {{64, 4, 0}, {64, 2, 1}, {64, 8, 1}, {64, 16, 1}, {6
                              {64, 8, 0}, {32, 8, 1}, {32, 16, 1}, {16, 16, 1}, {64, 2, 0},
                              {32, 8, 0}, {64, 16, 0}, {64, 32, 0}, {32, 16, 0},
                              {64, 4, 0, 1}, {64, 8, 0, 1}, {64, 2, 0, 1}, {64, 16, 0, 1},
-                             {32, 8, 0, 1}};
+                             {32, 8, 0, 1},
+                             {64, 4, 0, 0, 1}, {64, 8, 0, 0, 1}, {64, 16, 0, 0, 1}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -332,6 +335,12 @@ static bool pairs_ok(const tvlbm_ctx* c) {
   return !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC && c->d.nx % 2 == 0 && c->ld % 2 == 0;
 }
 
+// Two steps per launch: FP32 D2Q9/D2Q16, periodic in y, uniform rows.
+static bool two_ok(const tvlbm_ctx* c) {
+  return kVariants[c->variant].two && !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC &&
+         (c->hl.n == 3 || c->hl.n == 4);
+}
+
 static f32x2 splat2(float v) { return f32x2{v, v}; }
 
 // The single-grid step arguments restated in column-pair units.
@@ -374,7 +383,7 @@ static MarchArgs<f32x2> pair_args(const MarchArgs<float>& A) {
 template <typename R>
 static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
                      bool want_totals) {
-  const Variant v = kVariants[c->variant];
+  const Variant v = kVariants[c->variant].two ? kVariants[0] : kVariants[c->variant];
   if constexpr (std::is_same<R, float>::value) {
     if (v.pairs && mode == MODE_STEP && pairs_ok(c)) {
       const Geometry g = geometry(c->d.nx / 2, c->d.ny, v);
@@ -431,6 +440,24 @@ static int march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, vo
                  bool want_totals) {
   return c->f64 ? run_march_any<double>(c, mode, aux, src, dst, fields, want_totals)
                 : run_march_any<float>(c, mode, aux, src, dst, fields, want_totals);
+}
+
+// g^{k+2} from g^k in one launch (two_ok).
+static int march2(tvlbm_ctx* c, const void* src, void* dst) {
+  const Variant v = kVariants[c->variant];
+  MarchArgs<float> A;
+  std::memset(&A, 0, sizeof A);
+  A.lat = lat_of<float>(c);
+  A.inst = inst_of<float>(c);
+  A.width = 64;
+  A.rows = v.rows;
+  A.tiles_x = (int)ceil_div(c->d.nx, 62);
+  A.n_tiles = (int)(A.tiles_x * ceil_div(ceil_div(c->d.ny, v.rows), 4));
+  A.src = (const float*)src;
+  A.dst = (float*)dst;
+  const int nblocks = (int)(ceil_div(A.n_tiles, 8) * 8);
+  HIPCHK(c, launch_march2(c->hl.n, c->comp, A, nblocks, c->st));
+  return TVLBM_OK;
 }
 
 static size_t esize(const tvlbm_ctx* c) { return c->f64 ? 8 : 4; }
@@ -592,6 +619,17 @@ int tvlbm_set_populations(tvlbm_ctx* c, const void* f) {
 int tvlbm_step(tvlbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, TVLBM_EINVAL, "nsteps");
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
+  if (two_ok(c)) {
+    // the last launch is a single step, so that the other buffer keeps
+    // g^{k-1}, from which the populations and moments of step k are formed
+    for (int32_t p = 0; p < (nsteps - 1) / 2; ++p) {
+      int rc = march2(c, c->buf[c->cur], c->buf[c->cur ^ 1]);
+      if (rc) return rc;
+      c->cur ^= 1;
+      c->step += 2;
+    }
+    nsteps -= 2 * ((nsteps - 1) / 2);
+  }
   for (int32_t s = 0; s < nsteps; ++s) {
     int rc = march(c, MODE_STEP, 0, c->buf[c->cur], c->buf[c->cur ^ 1], nullptr, false);
     if (rc) return rc;

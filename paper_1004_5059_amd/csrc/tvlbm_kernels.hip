@@ -438,6 +438,200 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
 }
 
 
+// ----------------------------------------------- two steps per sweep --
+// k_march2: g^{k+2} from g^k in one pass over the grid (periodic in x and y,
+// uniform rows, FP32), without storing g^{k+1}: each population is read and
+// written once per two steps.  A wavefront owns a strip of 62 output columns
+// with one halo lane on each side, and a segment of output rows [j0, j1).
+// Along the segment it forms g^{k+1} on rows j0-1 .. j1 as the one-step
+// march does (centre and upstream column loaded, the x-pulled value of the
+// previous row kept per population), and one row behind it g^{k+2}: the x
+// part of the second remap takes the upstream column's g^{k+1} from the
+// neighbouring lane (a DPP shift by one lane), the y part keeps the x-pulled
+// values of the previous two rows in registers.  Every output cell sees the
+// same operations, in the same order, as under two one-step launches.
+constexpr int STRIP2 = 62;          // output columns per wavefront
+constexpr int DPP_PREV = 0x138;     // wave_shr:1 -- lane l reads lane l-1
+constexpr int DPP_NEXT = 0x130;     // wave_shl:1 -- lane l reads lane l+1
+
+template <int CTRL>
+__device__ __forceinline__ float lane_from(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+// moments, Hermite equilibrium and BGK of one cell, result in registers
+template <int N, int ORD, bool COMP>
+__device__ __forceinline__ void collide_regs(const Lat<float>& L, const Inst<float>& P,
+                                             const float (&d)[N * N], float (&g)[N * N]) {
+  float drho, jx, jy, ed;
+  cell_moments<float, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<float> F = fields_from(drho, jx, jy, ed);
+  EqNodes<float, N> E;
+  eq_nodes<float, N, ORD>(L, F, E);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    float Fa, Ka, Na;
+    eq_anode<float, N, ORD>(L, E, a, Fa, Ka, Na);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      g[l] = bgk(d[l], P.oww[l], P.omo, eq_dev<float, N, ORD>(L, E, a, b, Fa, Ka, Na));
+    }
+  }
+}
+
+__device__ __forceinline__ int wrap_row(int j, int ny) {
+  j %= ny;
+  return j < 0 ? j + ny : j;
+}
+
+template <int N, int ORD, bool COMP, int DIR>
+__device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, int im, int ip,
+                                           bool active, int j0, int j1) {
+  constexpr int Q = N * N;
+  const Lat<float>& L = A.lat;
+  const Inst<float>& P = A.inst;
+  const int ny = P.ny;
+  const int64_t plane = P.plane;
+  const uint32_t ld = (uint32_t)P.ld;
+  const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(float));
+  const rsrc_t s = make_rsrc(A.src + P.off, bytes);
+  const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
+  const int nout = j1 - j0;
+  const int jf = DIR > 0 ? j0 : j1 - 1;  // first output row
+
+  // first-step rows r_t = jf + (t - 1) DIR, t = 0 .. nout + 1; before r_0,
+  // lead populations need X^k of the row behind it, trail ones of r_0 itself
+  float hp[Q];
+  {
+    const int r0 = wrap_row(jf - DIR, ny);
+    const RowOff ob = row_off((uint32_t)wrap_row(r0 - DIR, ny) * ld, ic, im, ip);
+    const RowOff of = row_off((uint32_t)r0 * ld, ic, im, ip);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        if (sg == DIR)
+          hp[l] = xpull<float, N>(L, s, (uint32_t)(l * plane), a, ob);
+        else if (sg == -DIR)
+          hp[l] = xpull<float, N>(L, s, (uint32_t)(l * plane), a, of);
+        else
+          hp[l] = 0.0f;
+      }
+    }
+  }
+
+  float y1[Q], y2[Q];  // x-pulled g^{k+1} of the previous row and the one before
+#pragma unroll
+  for (int l = 0; l < Q; ++l) y1[l] = y2[l] = 0.0f;
+  for (int t = 0; t < nout + 2; ++t) {
+    const int r = wrap_row(jf + (t - 1) * DIR, ny);
+    const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
+    const RowOff on = row_off((uint32_t)wrap_row(r + DIR, ny) * ld, ic, im, ip);
+    float d[Q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        const uint32_t pl = (uint32_t)(l * plane);
+        if (sg == DIR) {  // lead
+          const float hn = xpull<float, N>(L, s, pl, a, oj);
+          d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
+          hp[l] = hn;
+        } else if (sg == -DIR) {  // trail
+          const float hn = xpull<float, N>(L, s, pl, a, on);
+          d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
+          hp[l] = hn;
+        } else {
+          d[l] = xpull<float, N>(L, s, pl, a, oj);
+        }
+      }
+    }
+    float g[Q];
+    collide_regs<N, ORD, COMP>(L, P, d, g);
+    // x part of the second remap, upstream column from the neighbouring lane
+    float x[Q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const int sa = node_sign<N>(a);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        if (sa > 0)
+          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
+        else if (sa < 0)
+          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
+        else
+          x[l] = g[l];
+      }
+    }
+    if (t >= 2) {  // second step on output row m = r - DIR
+      const uint32_t om = (uint32_t)wrap_row(r - DIR, ny) * ld + (uint32_t)ic;
+      float e[Q];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const int sg = node_sign<N>(b);
+          if (sg == DIR)
+            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * y2[l]);
+          else if (sg == -DIR)
+            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * x[l]);
+          else
+            e[l] = y1[l];
+        }
+      }
+      float g2[Q];
+      collide_regs<N, ORD, COMP>(L, P, e, g2);
+      if (active) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) bst(dst, om, (uint32_t)(l * plane), g2[l]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        if (node_sign<N>(b) == DIR) y2[l] = y1[l];
+        y1[l] = x[l];
+      }
+    }
+  }
+}
+
+// One workgroup = 4 wavefronts = 4 consecutive row segments of one strip.
+template <int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_march2(const MarchArgs<float> A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;  // multiple of 8
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (t >= A.n_tiles) return;
+  const int nx = A.inst.nx, ny = A.inst.ny;
+  const int tx = t % A.tiles_x, ty = t / A.tiles_x;
+  const int group = ty * 4 + wave;
+  const int j0 = group * A.rows;
+  if (j0 >= ny) return;  // wave-uniform
+  const int j1 = min(j0 + A.rows, ny);
+  const int col = tx * STRIP2 - 1 + lane;  // lanes 0 and 63 are halo
+  const bool active = lane >= 1 && lane <= STRIP2 && col < nx;
+  int ic = col % nx;
+  ic = ic < 0 ? ic + nx : ic;
+  const int im = ic == 0 ? nx - 1 : ic - 1;
+  const int ip = ic == nx - 1 ? 0 : ic + 1;
+  if (group & 1)
+    march2_dir<N, ORD, COMP, -1>(A, ic, im, ip, active, j0, j1);
+  else
+    march2_dir<N, ORD, COMP, +1>(A, ic, im, ip, active, j0, j1);
+}
+
 // ------------------------------------------------------- non-uniform rows --
 // Wall mass through a wall with non-uniform rows: the rows listed in inc[b]
 // carry the length len across the wall.
@@ -843,6 +1037,20 @@ static hipError_t march_pairs_lat(int n, const MarchArgs<f32x2>& A, int nblocks,
 hipError_t launch_march_pairs(int n, bool comp, const MarchArgs<f32x2>& A, int nblocks,
                               hipStream_t st) {
   return comp ? march_pairs_lat<true>(n, A, nblocks, st) : march_pairs_lat<false>(n, A, nblocks, st);
+}
+
+template <bool COMP>
+static hipError_t march2_lat(int n, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (n) {
+    case 3: hipLaunchKernelGGL((k_march2<3, 2, COMP>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_march2<4, 3, COMP>), g, b, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_march2(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
+  return comp ? march2_lat<true>(n, A, nblocks, st) : march2_lat<false>(n, A, nblocks, st);
 }
 
 template <typename R, bool COMP>

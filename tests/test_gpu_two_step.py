@@ -1,0 +1,117 @@
+"""The two-steps-per-launch variants (g^{k+2} from g^k in one sweep) against
+the one-step march: bitwise equal populations, fields and totals after odd
+and even step counts, on widths around the 62-column strips and on heights
+down to two rows, D2Q9 and D2Q16, compensated and plain sums; the grids
+the variant does not apply to (FP64, walls, D2Q36) run the one-step march;
+and the oracle on a ragged grid."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_common import c0_inputs, make_pair, rel_inf  # noqa: E402
+from paper_1004_5059_amd import inputs, tvlbm  # noqa: E402
+from paper_1004_5059_amd.tvlbm import Solver  # noqa: E402
+
+# the variant table's two-step entries (output rows per segment 4, 8, 16)
+TWO = [19, 20, 21]
+
+
+def _solver(nx, ny, n, variant, dtype="f32", compensated=True, walls=False, tau=0.7):
+    s = Solver(nx, ny, n_gh=n, dtype=dtype, tau=tau, compensated=compensated, walls=walls,
+               wall_hi=(0.03, 1.05))
+    s.set_variant(variant)
+    return s
+
+
+def _state(s):
+    F, tot = s.moments()
+    return s.populations().cpu().numpy(), F.cpu().numpy(), np.asarray(tot)
+
+
+def test_variant_table_has_the_two_step_entries():
+    assert tvlbm.tvlbm_num_variants() == 22
+
+
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (5, 3), (61, 9), (62, 17), (63, 2), (124, 33),
+                                   (125, 40), (190, 5)])
+def test_two_step_matches_one_step_bitwise(n, nx, ny):
+    fields, noise = c0_inputs(nx, ny, q=n * n, seed=nx + ny)
+    ref = _solver(nx, ny, n, 0)
+    ref.set_fields(*fields, noise)
+    runs = []
+    for v in TWO:
+        s = _solver(nx, ny, n, v)
+        s.set_fields(*fields, noise)
+        runs.append(s)
+    for k in (1, 2, 3, 5, 8):  # cumulative 1, 3, 6, 11, 19 steps
+        ref.step(k)
+        want = _state(ref)
+        for v, s in zip(TWO, runs):
+            s.step(k)
+            got = _state(s)
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), (v, k)
+    for s in runs + [ref]:
+        s.close()
+
+
+@pytest.mark.parametrize("compensated", [True, False])
+def test_two_step_plain_and_compensated_sums(compensated):
+    nx, ny = 130, 37
+    fields, noise = c0_inputs(nx, ny, q=16, seed=5)
+    a, b = _solver(nx, ny, 4, 0, compensated=compensated), _solver(nx, ny, 4, 20, compensated=compensated)
+    for s in (a, b):
+        s.set_fields(*fields, noise)
+        s.step(14)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    a.close(), b.close()
+
+
+@pytest.mark.parametrize("kw", [dict(dtype="f64"), dict(walls=True), dict(n=6)])
+def test_grids_outside_the_two_step_kernel_run_the_one_step_march(kw):
+    n = kw.pop("n", 4)
+    nx, ny = 70, 29
+    fields, noise = c0_inputs(nx, ny, q=n * n, seed=9)
+    a, b = _solver(nx, ny, n, 0, **kw), _solver(nx, ny, n, 20, **kw)
+    for s in (a, b):
+        s.set_fields(*fields, noise)
+        s.step(9)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    a.close(), b.close()
+
+
+@pytest.mark.parametrize("variant", TWO)
+def test_two_step_against_the_oracle(variant):
+    """D2Q16 FP32 on a ragged 131 x 45 grid, 13 steps (6 two-step launches
+    and a single step), every population within 1e-5 of the FP64 oracle,
+    mass and energy conserved."""
+    nx, ny, K = 131, 45, 13
+    s, g = make_pair(nx, ny, n=4, dtype="f32", tau=0.6, variant=variant)
+    fields = inputs.smoothed_density_fields(nx, ny, std=0.01, t_amp=0.05, seed=3)
+    noise = inputs.population_noise(16, ny, nx, amp=1e-4, seed=4)
+    s.set_fields(*fields, noise)
+    _, t0 = s.moments()
+    s.step(K)
+    _, t1 = s.moments()
+    fr = g.run(g.set_fields(*fields, noise), K)
+    assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-5
+    assert abs(t1[0] - t0[0]) / t0[0] <= 1e-6 and abs(t1[3] - t0[3]) / t0[3] <= 1e-6
+    s.close()
+
+
+def test_two_step_full_size_bitwise():
+    """1024 x 1024 D2Q16, the benchmark's initial state, 11 steps: every
+    population equal to the one-step march's."""
+    N = 1024
+    fields = inputs.smoothed_density_fields(N, N, std=0.01, t_amp=0.05, seed=1)
+    out = []
+    for v in (0, 20):
+        s = _solver(N, N, 4, v, tau=0.6)
+        s.set_fields(*fields)
+        s.step(11)
+        out.append(s.populations().cpu().numpy())
+        s.close()
+    assert np.array_equal(out[0], out[1])
