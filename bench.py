@@ -45,6 +45,7 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
     else:
         s.set_variant(variant)
         tune = {}
+    k = s.steps_per_launch()  # 2: the variant sweeps the grid once per two steps
     s.step(warmup)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
@@ -59,13 +60,16 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
     s.close()
     q = n * n
     cells = size * size
-    launch_s = ms / 1e3 / steps
+    launch_s = ms / 1e3 / steps * k
     esz = 4 if dtype == "f32" else 8
-    bytes_per_launch = 2 * esz * q * cells  # one read + one write per population
+    # algorithmic bytes: one read and one write per population per cell-update
+    bytes_per_launch = 2 * esz * q * cells * k
     return {
         "mlups": cells * steps / (ms / 1e3) / 1e6,
         "ms_per_step": ms / steps,
         "variant": variant,
+        "steps_per_launch": k,
+        "kernel": "k_march2 (two steps per launch)" if k == 2 else "k_march (one step per launch)",
         "tune_ms": {str(k): round(v, 5) for k, v in tune.items()},
         "achieved_gbs": bytes_per_launch / launch_s / 1e9,
         "bytes_per_launch": bytes_per_launch,
@@ -288,14 +292,15 @@ def cpu_baseline(size: int, target_s: float = 12.0):
             "sample": f"{steps} FP64 oracle steps of the {size}x{size} D2Q16 workload"}
 
 
-def traffic_from_profile():
+def traffic_from_profile(steps_per_launch: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source and on the same kind of launch
+    (one or two steps)."""
     p = os.path.join(ROOT, "profiles", "fused_step_d2q16_1024_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_hash") != _kernel_hash():
+    if d.get("kernel_hash") != _kernel_hash() or d.get("steps_per_launch", 1) != steps_per_launch:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -375,6 +380,12 @@ def main():
                                            not args.batched_load_only)
     cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
     achieved = r16["achieved_gbs"]
+    traffic = traffic_from_profile(r16["steps_per_launch"])
+    # HBM bytes actually moved per second (counted traffic per launch over
+    # the timed launch duration): below the algorithmic rate when a launch
+    # advances two steps on one read and one write
+    measured = None if traffic is None else \
+        traffic / (r16["ms_per_step"] * r16["steps_per_launch"] / 1e3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(r16["mlups"], 1),
@@ -393,7 +404,11 @@ def main():
                    "lattice": "D2Q16", "eq_order": 3, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile()},
+                     "traffic": traffic,
+                     "kernel": r16["kernel"], "steps_per_launch": r16["steps_per_launch"],
+                     "algorithmic_bytes_per_launch": r16["bytes_per_launch"],
+                     "measured_gbs": None if measured is None else round(measured, 1),
+                     "measured_frac": None if measured is None else round(measured / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
         "variant": r16["variant"],
         "d2q36": None if r36 is None else {
@@ -403,10 +418,12 @@ def main():
         "autotune_ms_per_step": r16["tune_ms"],
         "d2q16_4096": None if big is None else {
             "mlups": round(big["mlups"], 1), "achieved_gbs": round(big["achieved_gbs"], 1),
-            "frac": round(big["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": big["variant"]},
+            "frac": round(big["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": big["variant"],
+            "steps_per_launch": big["steps_per_launch"]},
         "d2q16_f64": None if r64 is None else {
             "mlups": round(r64["mlups"], 1), "achieved_gbs": round(r64["achieved_gbs"], 1),
-            "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": r64["variant"]},
+            "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4), "variant": r64["variant"],
+            "steps_per_launch": r64["steps_per_launch"]},
         "c0_64x64_f64": c0,
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
         "batched": bat,

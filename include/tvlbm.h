@@ -144,10 +144,20 @@ int tvlbm_save(tvlbm_ctx *ctx, const char *path);
 int tvlbm_load(tvlbm_ctx *ctx, const char *path);
 
 /* Launch-shape variant of the fused step kernel (rows per wavefront and
- * waves per workgroup); all variants compute identical results.  0 = the
- * default.  tvlbm_num_variants gives the count. */
+ * waves per workgroup); all variants compute identical results, bit for
+ * bit.  0 = the default.  tvlbm_num_variants gives the count.  Some
+ * variants advance two steps per launch (g^{k+2} from g^k in one sweep,
+ * Sec. II's collide-and-stream map applied twice, each population read and
+ * written once per two steps) on the grids that kernel covers: FP32, n_gh
+ * 3 or 4, periodic in y, uniform rows; elsewhere they run variant 0.
+ * tvlbm_step(ctx, n) with such a variant makes floor((n-1)/2) two-step
+ * launches and one or two single steps, so that the state after the call
+ * is the same as with single steps. */
 int tvlbm_num_variants(void);
 int tvlbm_set_variant(tvlbm_ctx *ctx, int32_t variant);
+/* Steps the step kernel advances per launch with the current variant on
+ * this grid: 1 or 2, written to *k (host).  EINVAL for NULL arguments. */
+int tvlbm_steps_per_launch(const tvlbm_ctx *ctx, int32_t *k);
 
 const char *tvlbm_strerror(int code);
 const char *tvlbm_last_error(const tvlbm_ctx *ctx);

@@ -38,7 +38,8 @@ const Variant kVariants[] = {{64, 4, 0}, {64, 2, 1}, {64, 8, 1}, {64, 16, 1}, {6
                              {32, 8, 0}, {64, 16, 0}, {64, 32, 0}, {32, 16, 0},
                              {64, 4, 0, 1}, {64, 8, 0, 1}, {64, 2, 0, 1}, {64, 16, 0, 1},
                              {32, 8, 0, 1},
-                             {64, 4, 0, 0, 1}, {64, 8, 0, 0, 1}, {64, 16, 0, 0, 1}};
+                             {64, 3, 0, 0, 1}, {64, 4, 0, 0, 1}, {64, 5, 0, 0, 1},
+                             {64, 6, 0, 0, 1}, {64, 8, 0, 0, 1}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -766,6 +767,12 @@ int tvlbm_lattice_table(int32_t n_gh, int32_t eq_order, double cfl, int32_t cfl_
   if (w) std::memcpy(w, hl.w, sizeof(double) * q);
   if (shift) std::memcpy(shift, hl.shift, sizeof(double) * 2 * q);
   if (lambda) *lambda = hl.lambda;
+  return TVLBM_OK;
+}
+
+int tvlbm_steps_per_launch(const tvlbm_ctx* c, int32_t* k) {
+  if (!c || !k) return TVLBM_EINVAL;
+  *k = two_ok(c) ? 2 : 1;
   return TVLBM_OK;
 }
 

@@ -159,6 +159,7 @@ def lib():
         "tvlbm_load": [_vp, ctypes.c_char_p],
         "tvlbm_num_variants": [],
         "tvlbm_set_variant": [_vp, ctypes.c_int32],
+        "tvlbm_steps_per_launch": [_vp, ctypes.POINTER(ctypes.c_int32)],
         "tvlbm_strerror": [ctypes.c_int],
         "tvlbm_last_error": [_vp],
         "tvlbm_batch_sizes": [ctypes.POINTER(tvlbm_batch_desc), _i64p, _i64p],
@@ -312,6 +313,12 @@ def tvlbm_set_variant(ctx, v: int):
     _check(lib().tvlbm_set_variant(ctx, int(v)), ctx)
 
 
+def tvlbm_steps_per_launch(ctx) -> int:
+    k = ctypes.c_int32()
+    _check(lib().tvlbm_steps_per_launch(ctx, ctypes.byref(k)), ctx)
+    return k.value
+
+
 # ------------------------------------------------------------- convenience --
 class Solver:
     """One TVLBM grid on the current CUDA/HIP device.
@@ -422,6 +429,9 @@ class Solver:
 
     def set_variant(self, v: int):
         tvlbm_set_variant(self.ctx, v)
+
+    def steps_per_launch(self) -> int:
+        return tvlbm_steps_per_launch(self.ctx)
 
 
 # ----------------------------------------------------------------- batched --

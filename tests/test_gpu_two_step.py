@@ -14,8 +14,8 @@ from gpu_common import c0_inputs, make_pair, rel_inf  # noqa: E402
 from paper_1004_5059_amd import inputs, tvlbm  # noqa: E402
 from paper_1004_5059_amd.tvlbm import Solver  # noqa: E402
 
-# the variant table's two-step entries (output rows per segment 4, 8, 16)
-TWO = [19, 20, 21]
+# the variant table's two-step entries (output rows per segment 3, 4, 5, 6, 8)
+TWO = [19, 20, 21, 22, 23]
 
 
 def _solver(nx, ny, n, variant, dtype="f32", compensated=True, walls=False, tau=0.7):
@@ -31,7 +31,19 @@ def _state(s):
 
 
 def test_variant_table_has_the_two_step_entries():
-    assert tvlbm.tvlbm_num_variants() == 22
+    assert tvlbm.tvlbm_num_variants() == 24
+    s = _solver(64, 16, 4, TWO[0])
+    assert s.steps_per_launch() == 2
+    s.set_variant(0)
+    assert s.steps_per_launch() == 1
+    s.close()
+    for kw in (dict(dtype="f64"), dict(walls=True)):
+        s = _solver(64, 16, 4, TWO[0], **kw)
+        assert s.steps_per_launch() == 1
+        s.close()
+    s = _solver(64, 16, 6, TWO[0])
+    assert s.steps_per_launch() == 1
+    s.close()
 
 
 @pytest.mark.parametrize("n", [3, 4])
@@ -62,7 +74,7 @@ def test_two_step_matches_one_step_bitwise(n, nx, ny):
 def test_two_step_plain_and_compensated_sums(compensated):
     nx, ny = 130, 37
     fields, noise = c0_inputs(nx, ny, q=16, seed=5)
-    a, b = _solver(nx, ny, 4, 0, compensated=compensated), _solver(nx, ny, 4, 20, compensated=compensated)
+    a, b = _solver(nx, ny, 4, 0, compensated=compensated), _solver(nx, ny, 4, 22, compensated=compensated)
     for s in (a, b):
         s.set_fields(*fields, noise)
         s.step(14)
@@ -75,7 +87,7 @@ def test_grids_outside_the_two_step_kernel_run_the_one_step_march(kw):
     n = kw.pop("n", 4)
     nx, ny = 70, 29
     fields, noise = c0_inputs(nx, ny, q=n * n, seed=9)
-    a, b = _solver(nx, ny, n, 0, **kw), _solver(nx, ny, n, 20, **kw)
+    a, b = _solver(nx, ny, n, 0, **kw), _solver(nx, ny, n, 22, **kw)
     for s in (a, b):
         s.set_fields(*fields, noise)
         s.step(9)
@@ -108,7 +120,7 @@ def test_two_step_full_size_bitwise():
     N = 1024
     fields = inputs.smoothed_density_fields(N, N, std=0.01, t_amp=0.05, seed=1)
     out = []
-    for v in (0, 20):
+    for v in (0, 22):
         s = _solver(N, N, 4, v, tau=0.6)
         s.set_fields(*fields)
         s.step(11)

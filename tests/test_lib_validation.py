@@ -74,6 +74,7 @@ def test_null_handles_are_rejected():
     assert L.tvlbm_batch_destroy(None) == T.TVLBM_EINVAL
     assert L.tvlbm_batch_set_tuning(None, None) == T.TVLBM_EINVAL
     assert L.tvlbm_init(None, None) == T.TVLBM_EINVAL
+    assert L.tvlbm_steps_per_launch(None, None) == T.TVLBM_EINVAL
 
 
 def test_every_error_code_has_a_message():
