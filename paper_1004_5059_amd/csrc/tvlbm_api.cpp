@@ -336,10 +336,10 @@ static bool pairs_ok(const tvlbm_ctx* c) {
   return !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC && c->d.nx % 2 == 0 && c->ld % 2 == 0;
 }
 
-// Two steps per launch: FP32 D2Q9/D2Q16, periodic in y, uniform rows.
+// Two steps per launch: FP32, periodic in y, uniform rows.
 static bool two_ok(const tvlbm_ctx* c) {
   return kVariants[c->variant].two && !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC &&
-         (c->hl.n == 3 || c->hl.n == 4);
+         (c->hl.n == 3 || c->hl.n == 4 || c->hl.n == 6);
 }
 
 static f32x2 splat2(float v) { return f32x2{v, v}; }

@@ -1045,6 +1045,7 @@ static hipError_t march2_lat(int n, const MarchArgs<float>& A, int nblocks, hipS
   switch (n) {
     case 3: hipLaunchKernelGGL((k_march2<3, 2, COMP>), g, b, 0, st, A); break;
     case 4: hipLaunchKernelGGL((k_march2<4, 3, COMP>), g, b, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((k_march2<6, 4, COMP>), g, b, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

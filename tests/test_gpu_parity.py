@@ -139,7 +139,7 @@ def test_run_to_run_deterministic():
 
 # launch variants bench.py's autotuner picks at 1024^2: one column per lane
 # (0: 64 x 4, 5: 64 x 8, 10: 32 x 8) and column pairs (14: 64 x 4, 16: 64 x 2)
-@pytest.mark.parametrize("n,variant", [(4, 0), (4, 14), (4, 16), (4, 22), (6, 5), (6, 10), (6, 14)])
+@pytest.mark.parametrize("n,variant", [(4, 0), (4, 14), (4, 16), (4, 22), (6, 5), (6, 10), (6, 14), (6, 22)])
 def test_c1_full_size_sampled_cells(n, variant):
     """1024x1024 periodic, FP32, tau 0.6, smoothed-density init, in the
     benchmark's launch configurations; 20 steps.  Each sampled cell is

@@ -1,8 +1,8 @@
 """The two-steps-per-launch variants (g^{k+2} from g^k in one sweep) against
 the one-step march: bitwise equal populations, fields and totals after odd
 and even step counts, on widths around the 62-column strips and on heights
-down to two rows, D2Q9 and D2Q16, compensated and plain sums; the grids
-the variant does not apply to (FP64, walls, D2Q36) run the one-step march;
+down to two rows, D2Q9, D2Q16 and D2Q36, compensated and plain sums; the
+grids the variant does not apply to (FP64, walls) run the one-step march;
 and the oracle on a ragged grid."""
 import numpy as np
 import pytest
@@ -42,11 +42,11 @@ def test_variant_table_has_the_two_step_entries():
         assert s.steps_per_launch() == 1
         s.close()
     s = _solver(64, 16, 6, TWO[0])
-    assert s.steps_per_launch() == 1
+    assert s.steps_per_launch() == 2
     s.close()
 
 
-@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("n", [3, 4, 6])
 @pytest.mark.parametrize("nx,ny", [(2, 2), (5, 3), (61, 9), (62, 17), (63, 2), (124, 33),
                                    (125, 40), (190, 5)])
 def test_two_step_matches_one_step_bitwise(n, nx, ny):
@@ -82,7 +82,8 @@ def test_two_step_plain_and_compensated_sums(compensated):
     a.close(), b.close()
 
 
-@pytest.mark.parametrize("kw", [dict(dtype="f64"), dict(walls=True), dict(n=6)])
+@pytest.mark.parametrize("kw", [dict(dtype="f64"), dict(walls=True), dict(n=6, walls=True),
+                                dict(n=6, dtype="f64")])
 def test_grids_outside_the_two_step_kernel_run_the_one_step_march(kw):
     n = kw.pop("n", 4)
     nx, ny = 70, 29
@@ -127,3 +128,18 @@ def test_two_step_full_size_bitwise():
         out.append(s.populations().cpu().numpy())
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_two_step_d2q36_against_the_oracle():
+    """D2Q36 (order 4) FP32, 77 x 40, 9 steps (4 two-step launches and a
+    single step), within 1e-5 of the FP64 oracle."""
+    nx, ny, K = 77, 40, 9
+    s, g = make_pair(nx, ny, n=6, dtype="f32", tau=0.6, variant=22)
+    assert s.steps_per_launch() == 2
+    fields = inputs.smoothed_density_fields(nx, ny, std=0.01, t_amp=0.05, seed=5)
+    noise = inputs.population_noise(36, ny, nx, amp=1e-4, seed=6)
+    s.set_fields(*fields, noise)
+    s.step(K)
+    fr = g.run(g.set_fields(*fields, noise), K)
+    assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-5
+    s.close()
