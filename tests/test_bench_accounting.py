@@ -1,0 +1,51 @@
+"""bench.py's roofline bookkeeping on the host: the counted HBM traffic is
+reported only for the kernel source and the kind of launch (one or two steps)
+it was taken on, and the committed counter file names its commands."""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _write(tmp_path, **kw):
+    d = {"kernel_hash": bench._kernel_hash(), "steps_per_launch": 2,
+         "hbm_bytes_per_launch": 123456789}
+    d.update(kw)
+    (tmp_path / "profiles").mkdir(exist_ok=True)
+    (tmp_path / "profiles" / "fused_step_d2q16_1024_counters.json").write_text(json.dumps(d))
+
+
+def test_traffic_needs_the_same_source_and_launch_kind(tmp_path, monkeypatch):
+    h = bench._kernel_hash()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "_kernel_hash", lambda: h)
+    _write(tmp_path)
+    assert bench.traffic_from_profile(2) == 123456789
+    assert bench.traffic_from_profile(1) is None
+    _write(tmp_path, kernel_hash="0" * 16)
+    assert bench.traffic_from_profile(2) is None
+    _write(tmp_path, steps_per_launch=None)
+    assert bench.traffic_from_profile(2) is None
+
+
+def test_traffic_without_a_counter_file(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profile(1) is None
+
+
+def test_committed_counter_file_is_complete():
+    d = json.load(open(os.path.join(ROOT, "profiles", "fused_step_d2q16_1024_counters.json")))
+    for k in ("kernel", "kernel_hash", "variant", "steps_per_launch", "fetch_size_kib_per_dispatch",
+              "write_size_kib_per_dispatch", "hbm_bytes_per_launch",
+              "algorithmic_bytes_per_launch", "commands"):
+        assert k in d, k
+    # reads = 2.0 x FETCH_SIZE, writes = 1.0 x WRITE_SIZE, KiB per dispatch
+    want = (d["fetch_calibration"] * d["fetch_size_kib_per_dispatch"]
+            + d["write_calibration"] * d["write_size_kib_per_dispatch"]) * 1024
+    assert abs(d["hbm_bytes_per_launch"] - want) <= 1
+    assert d["algorithmic_bytes_per_launch"] == 2 * 16 * 4 * 1024 * 1024 * d["steps_per_launch"]
+    assert all(c.startswith("rocprofv3 --pmc ") for c in d["commands"])
