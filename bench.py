@@ -80,7 +80,7 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
 def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls: bool = True,
            sched="auto", tau_g: float = 0.0, pscale: bool = False):
     """The finite-volume update, eq.(FVLB), on a size x size mesh: walls at the
-    first and last rows on the hyperbolic-tangent mesh of Sec. VIII scaled to
+    first and last rows on the hyperbolic-tangent mesh of Sec. X scaled to
     spacings 0.5 .. ~2.3 (or periodic and uniform), dt = 0.05, tau = 0.2."""
     import numpy as np
     import torch

@@ -98,7 +98,7 @@ typedef struct tvlbm_fv_schedule {
 int tvlbm_fv_set_schedule(tvlbm_fv *fv, const tvlbm_fv_schedule *s);
 
 /* Non-unit Prandtl number, eq.(FINAL) / eq.(OMEGAFVLB), and the
- * pressure-rescaled relaxation times of Sec. VIII.  tau_g > 0 (finite) adds
+ * pressure-rescaled relaxation times of Sec. IX.  tau_g > 0 (finite) adds
  * to the collision term
  *   -(1/tau_g) feq_l / (rho T^2) Pi : (c_l - u)(c_l - u),
  *   Pi_ij = sum_l (f_l - feq_l)(c_l - u)_i (c_l - u)_j,
@@ -116,7 +116,7 @@ int tvlbm_fv_set_prandtl(tvlbm_fv *fv, double tau_g, int32_t pressure_scaled);
  * TVLBM_FV_WALL_DIFFUSE (default): eq.(IMPOSITION) with the fixed wall
  *   equilibrium (wall_*_ux, wall_*_T of the descriptor); the flow slips and
  *   the temperature jumps at the wall by amounts of order tau.
- * TVLBM_FV_WALL_SLIP_FREE: Sec. VII / Appendix B: at every wall point and
+ * TVLBM_FV_WALL_SLIP_FREE: Sec. IX / Appendix B: at every wall point and
  *   step the wall equilibrium (u_eq, T_eq) is solved for, so that after the
  *   flux-weighted re-emission the point's own x velocity and temperature
  *   are the descriptor's wall values.  Newton's method on Appendix B's two

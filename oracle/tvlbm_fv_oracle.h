@@ -58,7 +58,7 @@ void orc_fv_free(orc_fv_grid *G);
  * (sign: see the collision term in the .c file),
  *   Pi_ij = sum_l (f_l - feq_l)(c_l - u)_i (c_l - u)_j   (eq.(FINAL));
  * tau_g <= 0 leaves single relaxation.  pscale: both relaxation times are
- * divided by the local pressure p = rho T (Sec. VIII). */
+ * divided by the local pressure p = rho T (Sec. IX). */
 void orc_fv_set_prandtl(orc_fv_grid *G, double tau_g, int pscale);
 /* Wall model.  0: eq.(IMPOSITION) with the fixed wall equilibrium (ulo, Tlo)
  * / (uhi, Thi).  1: slip-free walls, eq.(IMPOSITION2) read with the flux

@@ -68,7 +68,7 @@ __device__ __forceinline__ void eq_devs(const Lat<R>& L, const Fields<R>& F, R (
 
 // W = tau Omega of one cell from its deviations d (zero without collisions):
 // single relaxation W_l = feq_l - f_l, then, when set, the non-unit-Prandtl
-// term of eq.(FINAL) and the pressure-rescaled relaxation times (Sec. VIII):
+// term of eq.(FINAL) and the pressure-rescaled relaxation times (Sec. IX):
 //   W_l = ps [ (feq_l - f_l) - (tau / tau_g) feq_l Pi:(c_l - u)(c_l - u) / (rho T^2) ],
 //   Pi_ij = sum_l (f_l - feq_l) c_l^i c_l^j  (the central form of eq.(FINAL):
 //   f - feq carries no mass or momentum),  ps = rho T or 1.

@@ -107,7 +107,7 @@ def refined_wall_rows(h: int = 256, band: int = 16, ratio: int = 2) -> np.ndarra
 
 def tanh_mesh(length: float = 10.0, n_spacings: int = 60, beta: float = 2.3) -> np.ndarray:
     """Mesh-point coordinates (ascending, n_spacings + 1 points from 0 to
-    length) of the hyperbolic-tangent stretching of Sec. VIII:
+    length) of the hyperbolic-tangent stretching of Sec. X:
     y = (L/2)(1 + tanh(beta phi)/tanh(beta)), phi running from -1 to 1 in
     n_spacings equal steps (spacings smallest at both walls)."""
     phi = 1.0 - 2.0 * np.arange(n_spacings + 1) / n_spacings

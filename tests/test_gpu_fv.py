@@ -84,7 +84,7 @@ def test_periodic_nonuniform_mesh_conserves(dtype, tol):
                                          (6, "f32", 1e-5), (3, "f64", 1e-12)])
 def test_walls_on_the_tanh_mesh(n, dtype, tol, sched):
     """Walls at the first and last mesh rows (top moving, hotter), rows from
-    the hyperbolic-tangent stretching of Sec. VIII (41 points, beta 2.3),
+    the hyperbolic-tangent stretching of Sec. X (41 points, beta 2.3),
     scaled to spacings of 0.31 .. 7.0 mesh units so that c dt / dy stays
     below 0.6 for the fastest D2Q36 velocity (the explicit update is only
     conditionally stable).  After every step the net normal flux of each
@@ -165,7 +165,7 @@ def test_schedules_agree_over_many_steps():
 
 
 def _refined_couette(dtype, n=4):
-    """Sec. VIII: L_x x L_y = 0.2 x 10, N_x = 2 (dx = 0.1, periodic), N_y = 60
+    """Sec. X: L_x x L_y = 0.2 x 10, N_x = 2 (dx = 0.1, periodic), N_y = 60
     spacings of the tanh mesh (beta = 2.3, 0.016631 at the walls), walls at
     u = -0.1 / +0.1 and T = 1, tau = 0.01, dt = 0.005."""
     y = inputs.tanh_mesh(10.0, 60, 2.3)
@@ -293,7 +293,7 @@ def test_slip_free_walls_parity(n, dtype, tol, tau_g, sched):
 
 @pytest.mark.parametrize("Pr", [1.0 / 3.0, 1.0])
 def test_thermal_couette_of_sec7(Pr):
-    """The slip-free thermal Couette flow of Sec. VII: L_x x L_y = 0.2 x 10,
+    """The slip-free thermal Couette flow of Sec. IX: L_x x L_y = 0.2 x 10,
     N_x = 2, N_y = 120, dt = 0.005, tau = 0.1 with tau_g from the Prandtl
     number (Pr = tau_g / (2 tau + tau_g)), both times divided by the local
     pressure, Ec = U^2 / (c_v dT) = 2 (U = 0.2, dT = 0.02), D2Q36 (order 4)

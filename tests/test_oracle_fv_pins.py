@@ -124,7 +124,7 @@ def test_rest_state_between_resting_walls_is_a_fixed_point(lat):
 
 
 def test_tanh_mesh_spacings_are_the_papers():
-    """Sec. VIII: beta = 2.3, N_y = 60, L_y = 10 gives spacings from
+    """Sec. X: beta = 2.3, N_y = 60, L_y = 10 gives spacings from
     0.016631 at the walls to 0.391 in the middle (60 equal steps of phi)."""
     y = inputs.tanh_mesh(10.0, 60, 2.3)
     d = np.diff(y)

@@ -1,8 +1,8 @@
 """Pins of the FP64 oracle's non-unit-Prandtl collision, eq.(FINAL) with the
 finite-volume update eq.(FVLB), and of the pressure-rescaled relaxation times
-(Sec. VIII), against the transport coefficients of the hydrodynamic limit
+(Sec. IX), against the transport coefficients of the hydrodynamic limit
 (eta = c_v rho T tau tau_g / (2 tau + tau_g), conductivity c_P rho T tau,
-Sec. V) measured the way Sec. VI does: decay rates of a transverse shear
+Sec. IV) measured the way Sec. V does: decay rates of a transverse shear
 wave and of the isobaric thermal-diffusion mode.  Rates are compared as
 ratios against single relaxation on the same mesh, which cancels the
 discretisation error (the absolute single-relaxation rates are themselves

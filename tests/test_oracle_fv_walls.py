@@ -1,9 +1,9 @@
-"""Pins of the FP64 oracle's slip-free walls (Sec. VII, eq.(IMPOSITION2) with
+"""Pins of the FP64 oracle's slip-free walls (Sec. IX, eq.(IMPOSITION2) with
 the flux weights of eq.(IMPOSITION), the Newton iteration of Appendix B):
 the wall points carry exactly the prescribed velocity and temperature, the
 iteration converges in the few steps the paper reports, the wall mass
 balance is that of the diffuse walls, and the steady thermal Couette flow
-of Sec. VII (Ec = 2, Prandtl numbers 1 and 1/3, pressure-rescaled
+of Sec. IX (Ec = 2, Prandtl numbers 1 and 1/3, pressure-rescaled
 relaxation times) follows the no-slip hydrodynamic profile, where diffuse
 walls leave a slip and a temperature jump of order tau times the slope."""
 import numpy as np
