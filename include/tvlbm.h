@@ -148,8 +148,9 @@ int tvlbm_load(tvlbm_ctx *ctx, const char *path);
  * bit.  0 = the default.  tvlbm_num_variants gives the count.  Some
  * variants advance two steps per launch (g^{k+2} from g^k in one sweep,
  * Sec. II's collide-and-stream map applied twice, each population read and
- * written once per two steps) on the grids that kernel covers: FP32,
- * periodic in y, uniform rows; elsewhere they run variant 0.
+ * written once per two steps) on the grids that kernel covers (periodic
+ * in y, uniform rows; FP32 with n_gh 3, 4 or 6, FP64 with n_gh 3 or 4);
+ * elsewhere they run variant 0.
  * tvlbm_step(ctx, n) with such a variant makes floor((n-1)/2) two-step
  * launches and one or two single steps, so that the state after the call
  * is the same as with single steps. */

@@ -336,10 +336,11 @@ static bool pairs_ok(const tvlbm_ctx* c) {
   return !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC && c->d.nx % 2 == 0 && c->ld % 2 == 0;
 }
 
-// Two steps per launch: FP32, periodic in y, uniform rows.
+// Two steps per launch: periodic in y, uniform rows; FP32 D2Q9/D2Q16/D2Q36,
+// FP64 D2Q9/D2Q16 (FP64 D2Q36 would not fit the register file).
 static bool two_ok(const tvlbm_ctx* c) {
-  return kVariants[c->variant].two && !c->f64 && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC &&
-         (c->hl.n == 3 || c->hl.n == 4 || c->hl.n == 6);
+  return kVariants[c->variant].two && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC &&
+         (c->hl.n == 3 || c->hl.n == 4 || (c->hl.n == 6 && !c->f64));
 }
 
 static f32x2 splat2(float v) { return f32x2{v, v}; }
@@ -444,21 +445,25 @@ static int march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, vo
 }
 
 // g^{k+2} from g^k in one launch (two_ok).
-static int march2(tvlbm_ctx* c, const void* src, void* dst) {
+template <typename R>
+static int run_march2(tvlbm_ctx* c, const void* src, void* dst) {
   const Variant v = kVariants[c->variant];
-  MarchArgs<float> A;
+  MarchArgs<R> A;
   std::memset(&A, 0, sizeof A);
-  A.lat = lat_of<float>(c);
-  A.inst = inst_of<float>(c);
+  A.lat = lat_of<R>(c);
+  A.inst = inst_of<R>(c);
   A.width = 64;
   A.rows = v.rows;
   A.tiles_x = (int)ceil_div(c->d.nx, 62);
   A.n_tiles = (int)(A.tiles_x * ceil_div(ceil_div(c->d.ny, v.rows), 4));
-  A.src = (const float*)src;
-  A.dst = (float*)dst;
+  A.src = (const R*)src;
+  A.dst = (R*)dst;
   const int nblocks = (int)(ceil_div(A.n_tiles, 8) * 8);
   HIPCHK(c, launch_march2(c->hl.n, c->comp, A, nblocks, c->st));
   return TVLBM_OK;
+}
+static int march2(tvlbm_ctx* c, const void* src, void* dst) {
+  return c->f64 ? run_march2<double>(c, src, dst) : run_march2<float>(c, src, dst);
 }
 
 static size_t esize(const tvlbm_ctx* c) { return c->f64 ? 8 : 4; }

@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
 
 // ----------------------------------------------- two steps per sweep --
 // k_march2: g^{k+2} from g^k in one pass over the grid (periodic in x and y,
-// uniform rows, FP32), without storing g^{k+1}: each population is read and
+// uniform rows), without storing g^{k+1}: each population is read and
 // written once per two steps.  A wavefront owns a strip of 62 output columns
 // with one halo lane on each side, and a segment of output rows [j0, j1).
 // Along the segment it forms g^{k+1} on rows j0-1 .. j1 as the one-step
@@ -459,24 +459,31 @@ __device__ __forceinline__ float lane_from(float v) {
   return __builtin_bit_cast(float,
                             __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
+template <int CTRL>
+__device__ __forceinline__ double lane_from(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // moments, Hermite equilibrium and BGK of one cell, result in registers
-template <int N, int ORD, bool COMP>
-__device__ __forceinline__ void collide_regs(const Lat<float>& L, const Inst<float>& P,
-                                             const float (&d)[N * N], float (&g)[N * N]) {
-  float drho, jx, jy, ed;
-  cell_moments<float, N, COMP>(L, d, drho, jx, jy, ed);
-  const Fields<float> F = fields_from(drho, jx, jy, ed);
-  EqNodes<float, N> E;
-  eq_nodes<float, N, ORD>(L, F, E);
+template <typename R, int N, int ORD, bool COMP>
+__device__ __forceinline__ void collide_regs(const Lat<R>& L, const Inst<R>& P,
+                                             const R (&d)[N * N], R (&g)[N * N]) {
+  R drho, jx, jy, ed;
+  cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
+  const Fields<R> F = fields_from(drho, jx, jy, ed);
+  EqNodes<R, N> E;
+  eq_nodes<R, N, ORD>(L, F, E);
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    float Fa, Ka, Na;
-    eq_anode<float, N, ORD>(L, E, a, Fa, Ka, Na);
+    R Fa, Ka, Na;
+    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const int l = a * N + b;
-      g[l] = bgk(d[l], P.oww[l], P.omo, eq_dev<float, N, ORD>(L, E, a, b, Fa, Ka, Na));
+      g[l] = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
     }
   }
 }
@@ -486,16 +493,16 @@ __device__ __forceinline__ int wrap_row(int j, int ny) {
   return j < 0 ? j + ny : j;
 }
 
-template <int N, int ORD, bool COMP, int DIR>
-__device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, int im, int ip,
+template <typename R, int N, int ORD, bool COMP, int DIR>
+__device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im, int ip,
                                            bool active, int j0, int j1) {
   constexpr int Q = N * N;
-  const Lat<float>& L = A.lat;
-  const Inst<float>& P = A.inst;
+  const Lat<R>& L = A.lat;
+  const Inst<R>& P = A.inst;
   const int ny = P.ny;
   const int64_t plane = P.plane;
   const uint32_t ld = (uint32_t)P.ld;
-  const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(float));
+  const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(R));
   const rsrc_t s = make_rsrc(A.src + P.off, bytes);
   const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
   const int nout = j1 - j0;
@@ -503,7 +510,7 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
 
   // first-step rows r_t = jf + (t - 1) DIR, t = 0 .. nout + 1; before r_0,
   // lead populations need X^k of the row behind it, trail ones of r_0 itself
-  float hp[Q];
+  R hp[Q];
   {
     const int r0 = wrap_row(jf - DIR, ny);
     const RowOff ob = row_off((uint32_t)wrap_row(r0 - DIR, ny) * ld, ic, im, ip);
@@ -515,23 +522,23 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
         const int l = a * N + b;
         const int sg = node_sign<N>(b);
         if (sg == DIR)
-          hp[l] = xpull<float, N>(L, s, (uint32_t)(l * plane), a, ob);
+          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, ob);
         else if (sg == -DIR)
-          hp[l] = xpull<float, N>(L, s, (uint32_t)(l * plane), a, of);
+          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, of);
         else
-          hp[l] = 0.0f;
+          hp[l] = R(0);
       }
     }
   }
 
-  float y1[Q], y2[Q];  // x-pulled g^{k+1} of the previous row and the one before
+  R y1[Q], y2[Q];  // x-pulled g^{k+1} of the previous row and the one before
 #pragma unroll
-  for (int l = 0; l < Q; ++l) y1[l] = y2[l] = 0.0f;
+  for (int l = 0; l < Q; ++l) y1[l] = y2[l] = R(0);
   for (int t = 0; t < nout + 2; ++t) {
     const int r = wrap_row(jf + (t - 1) * DIR, ny);
     const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
     const RowOff on = row_off((uint32_t)wrap_row(r + DIR, ny) * ld, ic, im, ip);
-    float d[Q];
+    R d[Q];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
 #pragma unroll
@@ -540,22 +547,22 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
         const int sg = node_sign<N>(b);
         const uint32_t pl = (uint32_t)(l * plane);
         if (sg == DIR) {  // lead
-          const float hn = xpull<float, N>(L, s, pl, a, oj);
+          const R hn = xpull<R, N>(L, s, pl, a, oj);
           d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
           hp[l] = hn;
         } else if (sg == -DIR) {  // trail
-          const float hn = xpull<float, N>(L, s, pl, a, on);
+          const R hn = xpull<R, N>(L, s, pl, a, on);
           d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
           hp[l] = hn;
         } else {
-          d[l] = xpull<float, N>(L, s, pl, a, oj);
+          d[l] = xpull<R, N>(L, s, pl, a, oj);
         }
       }
     }
-    float g[Q];
-    collide_regs<N, ORD, COMP>(L, P, d, g);
+    R g[Q];
+    collide_regs<R, N, ORD, COMP>(L, P, d, g);
     // x part of the second remap, upstream column from the neighbouring lane
-    float x[Q];
+    R x[Q];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       const int sa = node_sign<N>(a);
@@ -572,7 +579,7 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
     }
     if (t >= 2) {  // second step on output row m = r - DIR
       const uint32_t om = (uint32_t)wrap_row(r - DIR, ny) * ld + (uint32_t)ic;
-      float e[Q];
+      R e[Q];
 #pragma unroll
       for (int a = 0; a < N; ++a) {
 #pragma unroll
@@ -587,8 +594,8 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
             e[l] = y1[l];
         }
       }
-      float g2[Q];
-      collide_regs<N, ORD, COMP>(L, P, e, g2);
+      R g2[Q];
+      collide_regs<R, N, ORD, COMP>(L, P, e, g2);
       if (active) {
 #pragma unroll
         for (int l = 0; l < Q; ++l) bst(dst, om, (uint32_t)(l * plane), g2[l]);
@@ -607,8 +614,8 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<float>& A, int ic, in
 }
 
 // One workgroup = 4 wavefronts = 4 consecutive row segments of one strip.
-template <int N, int ORD, bool COMP>
-__global__ __launch_bounds__(256) void k_march2(const MarchArgs<float> A) {
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_march2(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nb = gridDim.x;  // multiple of 8
@@ -627,9 +634,9 @@ __global__ __launch_bounds__(256) void k_march2(const MarchArgs<float> A) {
   const int im = ic == 0 ? nx - 1 : ic - 1;
   const int ip = ic == nx - 1 ? 0 : ic + 1;
   if (group & 1)
-    march2_dir<N, ORD, COMP, -1>(A, ic, im, ip, active, j0, j1);
+    march2_dir<R, N, ORD, COMP, -1>(A, ic, im, ip, active, j0, j1);
   else
-    march2_dir<N, ORD, COMP, +1>(A, ic, im, ip, active, j0, j1);
+    march2_dir<R, N, ORD, COMP, +1>(A, ic, im, ip, active, j0, j1);
 }
 
 // ------------------------------------------------------- non-uniform rows --
@@ -1039,19 +1046,28 @@ hipError_t launch_march_pairs(int n, bool comp, const MarchArgs<f32x2>& A, int n
   return comp ? march_pairs_lat<true>(n, A, nblocks, st) : march_pairs_lat<false>(n, A, nblocks, st);
 }
 
-template <bool COMP>
-static hipError_t march2_lat(int n, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
+template <typename R, bool COMP>
+static hipError_t march2_lat(int n, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
   dim3 g(nblocks), b(256);
   switch (n) {
-    case 3: hipLaunchKernelGGL((k_march2<3, 2, COMP>), g, b, 0, st, A); break;
-    case 4: hipLaunchKernelGGL((k_march2<4, 3, COMP>), g, b, 0, st, A); break;
-    case 6: hipLaunchKernelGGL((k_march2<6, 4, COMP>), g, b, 0, st, A); break;
+    case 3: hipLaunchKernelGGL((k_march2<R, 3, 2, COMP>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_march2<R, 4, 3, COMP>), g, b, 0, st, A); break;
+    case 6:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_march2<R, 6, 4, COMP>), g, b, 0, st, A);
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 hipError_t launch_march2(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
-  return comp ? march2_lat<true>(n, A, nblocks, st) : march2_lat<false>(n, A, nblocks, st);
+  return comp ? march2_lat<float, true>(n, A, nblocks, st) : march2_lat<float, false>(n, A, nblocks, st);
+}
+hipError_t launch_march2(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st) {
+  (void)comp;  // FP64 sums need no compensation
+  return march2_lat<double, false>(n, A, nblocks, st);
 }
 
 template <typename R, bool COMP>

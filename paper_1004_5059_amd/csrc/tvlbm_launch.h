@@ -54,10 +54,12 @@ hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start
                                 hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<float>& A, int nblocks,
                         hipStream_t st);
-// Two steps per launch (g^{k+2} from g^k): FP32, grid periodic in x and y,
-// uniform rows, D2Q9, D2Q16 or D2Q36.  A.tiles_x = strips of 62 columns, A.rows =
-// output rows per wavefront segment, A.n_tiles = tiles_x * ceil(segments/4).
+// Two steps per launch (g^{k+2} from g^k): grid periodic in x and y, uniform
+// rows; FP32 D2Q9, D2Q16 or D2Q36, FP64 D2Q9 or D2Q16.  A.tiles_x = strips of
+// 62 columns, A.rows = output rows per wavefront segment, A.n_tiles =
+// tiles_x * ceil(segments/4).
 hipError_t launch_march2(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st);
+hipError_t launch_march2(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
                         hipStream_t st);
 hipError_t launch_init(int n, bool comp, const InitArgs<float>& A, hipStream_t st);

@@ -2,7 +2,8 @@
 the one-step march: bitwise equal populations, fields and totals after odd
 and even step counts, on widths around the 62-column strips and on heights
 down to two rows, D2Q9, D2Q16 and D2Q36, compensated and plain sums; the
-grids the variant does not apply to (FP64, walls) run the one-step march;
+grids the variant does not apply to (walls, FP64 D2Q36) run the one-step
+march; FP64 D2Q9/D2Q16 bitwise as well;
 and the oracle on a ragged grid."""
 import numpy as np
 import pytest
@@ -37,10 +38,15 @@ def test_variant_table_has_the_two_step_entries():
     s.set_variant(0)
     assert s.steps_per_launch() == 1
     s.close()
-    for kw in (dict(dtype="f64"), dict(walls=True)):
-        s = _solver(64, 16, 4, TWO[0], **kw)
-        assert s.steps_per_launch() == 1
-        s.close()
+    s = _solver(64, 16, 4, TWO[0], walls=True)
+    assert s.steps_per_launch() == 1
+    s.close()
+    s = _solver(64, 16, 4, TWO[0], dtype="f64")
+    assert s.steps_per_launch() == 2
+    s.close()
+    s = _solver(64, 16, 6, TWO[0], dtype="f64")
+    assert s.steps_per_launch() == 1
+    s.close()
     s = _solver(64, 16, 6, TWO[0])
     assert s.steps_per_launch() == 2
     s.close()
@@ -82,8 +88,8 @@ def test_two_step_plain_and_compensated_sums(compensated):
     a.close(), b.close()
 
 
-@pytest.mark.parametrize("kw", [dict(dtype="f64"), dict(walls=True), dict(n=6, walls=True),
-                                dict(n=6, dtype="f64")])
+@pytest.mark.parametrize("kw", [dict(walls=True), dict(n=6, walls=True), dict(n=6, dtype="f64"),
+                                dict(dtype="f64", walls=True)])
 def test_grids_outside_the_two_step_kernel_run_the_one_step_march(kw):
     n = kw.pop("n", 4)
     nx, ny = 70, 29
@@ -142,4 +148,32 @@ def test_two_step_d2q36_against_the_oracle():
     s.step(K)
     fr = g.run(g.set_fields(*fields, noise), K)
     assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("nx,ny", [(5, 3), (62, 17), (125, 40)])
+def test_two_step_fp64_matches_one_step_bitwise(n, nx, ny):
+    fields, noise = c0_inputs(nx, ny, q=n * n, seed=nx)
+    a, b = _solver(nx, ny, n, 0, dtype="f64"), _solver(nx, ny, n, 22, dtype="f64")
+    assert b.steps_per_launch() == 2
+    for s in (a, b):
+        s.set_fields(*fields, noise)
+    for k in (1, 4, 7):
+        a.step(k), b.step(k)
+        for x, y in zip(_state(a), _state(b)):
+            assert np.array_equal(x, y), k
+    a.close(), b.close()
+
+
+def test_two_step_fp64_against_the_oracle():
+    """D2Q16 FP64, 131 x 45, 13 steps, within 1e-12 of the oracle."""
+    nx, ny, K = 131, 45, 13
+    s, g = make_pair(nx, ny, n=4, dtype="f64", tau=0.6, variant=22)
+    fields = inputs.smoothed_density_fields(nx, ny, std=0.01, t_amp=0.05, seed=3)
+    noise = inputs.population_noise(16, ny, nx, amp=1e-4, seed=4)
+    s.set_fields(*fields, noise)
+    s.step(K)
+    fr = g.run(g.set_fields(*fields, noise), K)
+    assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-12
     s.close()
