@@ -177,3 +177,29 @@ def test_two_step_fp64_against_the_oracle():
     fr = g.run(g.set_fields(*fields, noise), K)
     assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-12
     s.close()
+
+
+def test_checkpoint_across_one_and_two_step_variants(tmp_path):
+    """Saved after 9 steps with a two-step variant (4 two-step launches and a
+    single step), loaded into a solver on the one-step variant, continued 6
+    steps: the same populations, fields and totals as 15 one-step steps."""
+    from paper_1004_5059_amd import tvlbm as T
+
+    nx, ny = 130, 37
+    fields, noise = c0_inputs(nx, ny, q=16, seed=8)
+    ref = _solver(nx, ny, 4, 0)
+    ref.set_fields(*fields, noise)
+    ref.step(15)
+    s = _solver(nx, ny, 4, 22)
+    s.set_fields(*fields, noise)
+    s.step(9)
+    p = str(tmp_path / "ck.bin")
+    T.tvlbm_save(s.ctx, p)
+    s.close()
+    t = _solver(nx, ny, 4, 0)
+    T.tvlbm_load(t.ctx, p)
+    assert t.step_count == 9
+    t.step(6)
+    for x, y in zip(_state(t), _state(ref)):
+        assert np.array_equal(x, y)
+    t.close(), ref.close()
