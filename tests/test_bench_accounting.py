@@ -49,3 +49,11 @@ def test_committed_counter_file_is_complete():
     assert abs(d["hbm_bytes_per_launch"] - want) <= 1
     assert d["algorithmic_bytes_per_launch"] == 2 * 16 * 4 * 1024 * 1024 * d["steps_per_launch"]
     assert all(c.startswith("rocprofv3 --pmc ") for c in d["commands"])
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
