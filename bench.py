@@ -229,10 +229,12 @@ def run_c0(steps: int = 200):
     from paper_1004_5059_amd import inputs
     from paper_1004_5059_amd.tvlbm import Solver
 
+    from paper_1004_5059_amd.autotune import autotune
+
     s = Solver(64, 64, n_gh=4, dtype="f64", tau=0.8, device="cuda:0")
     s.set_fields(*inputs.shear_wave_fields(64, 64, eps=0.01),
                  inputs.population_noise(16, 64, 64, amp=1e-4, seed=0))
-    s.step(5)
+    variant, _ = autotune(s, steps=20)
     s.set_fields(*inputs.shear_wave_fields(64, 64, eps=0.01),
                  inputs.population_noise(16, 64, 64, amp=1e-4, seed=0))
     torch.cuda.synchronize()
@@ -243,9 +245,11 @@ def run_c0(steps: int = 200):
     b.record(s.stream)
     b.synchronize()
     ms = a.elapsed_time(b)
+    k = s.steps_per_launch()
     s.close()
     return {"steps": steps, "ms": round(ms, 3), "us_per_step": round(ms * 1e3 / steps, 2),
-            "mlups": round(64 * 64 * steps / (ms / 1e3) / 1e6, 1)}
+            "mlups": round(64 * 64 * steps / (ms / 1e3) / 1e6, 1), "variant": variant,
+            "steps_per_launch": k}
 
 
 def copy_ceiling(mib: int = 1024, reps: int = 10):

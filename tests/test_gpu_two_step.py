@@ -203,3 +203,17 @@ def test_checkpoint_across_one_and_two_step_variants(tmp_path):
     for x, y in zip(_state(t), _state(ref)):
         assert np.array_equal(x, y)
     t.close(), ref.close()
+
+
+@pytest.mark.parametrize("variant", TWO)
+def test_c0_shear_wave_two_step_fp64(variant):
+    """The 64 x 64 FP64 case (tau 0.8, shear wave plus noise, 200 steps) on
+    the two-step variants: within 1e-12 of the oracle."""
+    s, g = make_pair(64, 64, n=4, dtype="f64", tau=0.8, variant=variant)
+    assert s.steps_per_launch() == 2
+    fields, noise = c0_inputs()
+    s.set_fields(*fields, noise)
+    s.step(200)
+    fr = g.run(g.set_fields(*fields, noise), 200)
+    assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-12
+    s.close()
