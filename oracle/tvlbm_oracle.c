@@ -11,8 +11,14 @@
  * moment identities and the tensor form of the Hermite expansion, exact
  * conservation, the equilibrium fixed point, integer shifts against a plain
  * array roll, the Fourier symbol of the remap, and the linearised shear-wave
- * eigenvalue.  The wall re-emission rule is pinned only by mass balance and
- * the rest-state fixed point (parity unpinned for its values).
+ * eigenvalue.  Non-uniform rows: the Fourier symbol of a shift by s/h rows
+ * on rows of height h, remap matrices derived by hand on a two-height mesh,
+ * the lengths that cross a wall and the emitted interval on that mesh.
+ * Totals: closed-form totals of row-wise equilibria on rows of different
+ * heights.  A NumPy mini-oracle (mini.py) agrees step by step.  The wall
+ * re-emission rule itself (which equilibrium the incident mass is emitted
+ * with) is pinned only by mass balance and the rest-state fixed point
+ * (parity unpinned for its values).
  */
 #include "tvlbm_oracle.h"
 

@@ -56,3 +56,28 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(np.abs(p[g != 0]), 1e-3, rtol=1e-12)
     assert np.all(np.sign(p[g != 0]) == -np.sign(g[g != 0]))
     assert p[3] == 0.0
+
+
+def test_gelu_matches_tabulated_normal_cdf():
+    """GELU(z) = z Phi(z) with Phi the standard normal CDF, here from its
+    table (Phi(-z) = 1 - Phi(z)); the tanh approximation of GELU is off by
+    ~1e-4 at z = 1 and fails this."""
+    phi = {0.5: 0.6914624612740131, 1.0: 0.8413447460685429, 1.5: 0.9331927987311419,
+           2.0: 0.9772498680518208, 2.5: 0.9937903346742238, 3.0: 0.9986501019683699}
+    z = np.array([0.0] + [s * v for v in phi for s in (1.0, -1.0)])
+    want = np.array([0.0] + [s * v * (phi[v] if s > 0 else 1.0 - phi[v])
+                             for v in phi for s in (1.0, -1.0)])
+    np.testing.assert_allclose(cn.gelu(z), want, rtol=1e-14, atol=1e-16)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2 at every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so
+    each update is lr g / (|g| + eps): after t steps p = -t lr sign(g) for
+    eps << |g|.  A bias correction with the wrong power of t fails at t >= 2."""
+    g = np.array([1.0, -2.0, 0.5, 3.0])
+    p = np.zeros(4)
+    m, v = np.zeros(4), np.zeros(4)
+    for t in range(1, 7):
+        cn.adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-14)
+        np.testing.assert_allclose(p, -t * 1e-3 * np.sign(g), rtol=1e-11)
