@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline (D2Q16, 1024²); batched steady solves/s vs plain"
 HBM_PEAK_GBS = 8000.0
+SCLK_HZ = 2.4e9  # MI355X peak engine clock
 
 
 def _kernel_hash() -> str:
@@ -48,19 +49,30 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
     k = s.steps_per_launch()  # 2: the variant sweeps the grid once per two steps
     s.step(warmup)
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(s.stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(s.stream)
     s.step(steps)
-    b.record(s.stream)
-    b.synchronize()
+    ev[1].record(s.stream)
+    # With two steps per launch, tvlbm_step makes (steps-1)//2 two-step
+    # launches and ends with one or two single steps (state semantics); time
+    # single-step launches on their own on the same stream, so that the
+    # two-step kernel's average launch duration can be separated.
+    n2 = (steps - 1) // 2 if k == 2 else 0
+    n1 = steps - 2 * n2
+    reps1 = 20
+    ev[2].record(s.stream)
+    for _ in range(reps1):
+        s.step(1)
+    ev[3].record(s.stream)
+    ev[3].synchronize()
     torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
+    ms = ev[0].elapsed_time(ev[1])
+    ms1 = ev[2].elapsed_time(ev[3]) / reps1
+    launch_ms = (ms - n1 * ms1) / n2 if n2 > 0 else ms / steps
     _, tot = s.moments()
     s.close()
     q = n * n
     cells = size * size
-    launch_s = ms / 1e3 / steps * k
     esz = 4 if dtype == "f32" else 8
     # algorithmic bytes: one read and one write per population per cell-update
     bytes_per_launch = 2 * esz * q * cells * k
@@ -69,9 +81,12 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
         "ms_per_step": ms / steps,
         "variant": variant,
         "steps_per_launch": k,
+        "launches": {"two_step": n2, "one_step": n1},
+        "launch_ms": launch_ms,
+        "one_step_launch_ms": ms1,
         "kernel": "k_march2 (two steps per launch)" if k == 2 else "k_march (one step per launch)",
         "tune_ms": {str(k): round(v, 5) for k, v in tune.items()},
-        "achieved_gbs": bytes_per_launch / launch_s / 1e9,
+        "achieved_gbs": bytes_per_launch / (launch_ms / 1e3) / 1e9,
         "bytes_per_launch": bytes_per_launch,
         "mass": float(tot[0]),
     }
@@ -253,26 +268,79 @@ def run_c0(steps: int = 200):
 
 
 def copy_ceiling(mib: int = 1024, reps: int = 10):
-    """Device-to-device copy of a buffer larger than the MALL: the achievable
-    HBM bandwidth ceiling (bytes read + bytes written per second)."""
+    """The library's 16-byte streaming copy kernel on two buffers of `mib`
+    MiB each (four times the 256 MB Infinity Cache): the HBM read + write
+    rate a streaming kernel reaches on this GPU."""
     import torch
 
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    from paper_1004_5059_amd.tvlbm import tvlbm_stream_copy
+
+    nbytes = mib * (1 << 20)
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
-    b.copy_(a)
+    st = torch.cuda.current_stream()
+    tvlbm_stream_copy(a, b, nbytes, st)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(st)
     for _ in range(reps):
-        b.copy_(a)
-    e1.record()
+        tvlbm_stream_copy(a, b, nbytes, st)
+    e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:: 1 << 16], b[:: 1 << 16]))
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "gbs": 2 * n * 4 / (ms / 1e3) / 1e9}
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms / 1e3) / 1e9,
+            "kernel": "k_stream_copy (16-byte grid-stride, library)", "copied": ok}
+
+
+def run_c2(tol: float = 1e-8, k: int = 100):
+    """The bounded thermal flow: 512 x 256 channel, rows refined 2:1 in
+    16-cell bands at both walls (288 rows), D2Q16, FP32, tau 0.7, walls
+    (u, T) = (0, 1) and (0.05, 1.1), from the uniform state to residual 1e-8
+    (K = 100); wall time, steps, per-step kernel time, mass drift and the
+    profile's distance from the closed-form thermal Couette solution."""
+    import numpy as np
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.tvlbm import Solver
+
+    dy = inputs.refined_wall_rows(h=256, band=16, ratio=2)
+    ny = len(dy)
+    s = Solver(512, ny, n_gh=4, dtype="f32", tau=0.7, dy=dy, walls=True, wall_lo=(0.0, 1.0),
+               wall_hi=(0.05, 1.1), device="cuda:0")
+    s.set_fields(*inputs.uniform_fields(512, ny))
+    m0 = s.moments()[1][0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv, steps, r = s.solve(3_000_000, tol, k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fld, tot = s.moments()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(200)
+    b.record(s.stream)
+    b.synchronize()
+    us_step = a.elapsed_time(b) * 1e3 / 200
+    s.close()
+    q = fld.double().cpu().numpy().mean(axis=2)
+    yb = np.concatenate([[0.0], np.cumsum(dy)])
+    yc = 0.5 * (yb[1:] + yb[:-1]) / yb[-1]
+    ucf = 0.05 * yc
+    tcf = 1.0 + 0.1 * yc + 0.05 ** 2 / 4.0 * yc * (1 - yc)
+    cells = 512 * ny
+    return {"converged": bool(conv), "steps": int(steps), "residual": r, "wall_s": round(wall, 3),
+            "us_per_step": round(us_step, 2), "mlups": round(cells / us_step, 1),
+            "achieved_gbs": round(128.0 * cells / (us_step * 1e-6) / 1e9, 1),
+            "mass_drift": float(abs(tot[0] - m0) / m0),
+            "couette_u_err": round(float(np.max(np.abs(q[1] - ucf)) / 0.05), 5),
+            "couette_T_err": round(float(np.max(np.abs(q[3] - tcf)) / 0.1), 5),
+            "kernel": "k_rows (non-uniform rows, diffuse walls)"}
 
 
 def cpu_baseline(size: int, target_s: float = 15.0):
@@ -297,17 +365,18 @@ def cpu_baseline(size: int, target_s: float = 15.0):
             "sample": f"{steps} FP64 oracle steps of the {size}x{size} D2Q16 workload"}
 
 
-def traffic_from_profile(steps_per_launch: int):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source and on the same kind of launch
-    (one or two steps)."""
+def counters_from_profile(steps_per_launch: int, variant: int):
+    """Counted HBM bytes and VALU wave-instructions per launch of the step
+    kernel, from committed rocprofv3 counter runs, if they were taken on the
+    current kernel source and on the same launch variant; else None."""
     p = os.path.join(ROOT, "profiles", "fused_step_d2q16_1024_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_hash") != _kernel_hash() or d.get("steps_per_launch", 1) != steps_per_launch:
+    if (d.get("kernel_hash") != _kernel_hash() or d.get("steps_per_launch", 1) != steps_per_launch
+            or d.get("variant") != variant):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def main():
@@ -330,6 +399,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 lines (1024^2 and 64^2)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
     ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume legs")
+    ap.add_argument("--no-c2", action="store_true", help="skip the bounded-flow steady solve")
     ap.add_argument("--fv-only", action="store_true", help="run only the finite-volume legs")
     ap.add_argument("--fv-size", type=int, default=1024, help="mesh size of the finite-volume legs")
     ap.add_argument("--batched-load-only", action="store_true",
@@ -383,14 +453,20 @@ def main():
     cp = None if args.no_copy else leg("copy ceiling", copy_ceiling)
     bat = None if args.no_batched else leg("batched", run_batched, 256, 2, 1e-8, 100,
                                            not args.batched_load_only)
+    c2 = None if args.no_c2 else leg("C2 bounded flow", run_c2)
     cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
     achieved = r16["achieved_gbs"]
-    traffic = traffic_from_profile(r16["steps_per_launch"])
-    # HBM bytes actually moved per second (counted traffic per launch over
-    # the timed launch duration): below the algorithmic rate when a launch
-    # advances two steps on one read and one write
-    measured = None if traffic is None else \
-        traffic / (r16["ms_per_step"] * r16["steps_per_launch"] / 1e3) / 1e9
+    prof = counters_from_profile(r16["steps_per_launch"], r16["variant"])
+    traffic = None if prof is None else prof.get("hbm_bytes_per_launch")
+    launch_s = r16["launch_ms"] / 1e3
+    # HBM bytes actually moved per second: counted traffic per launch over
+    # the live average launch duration (below the algorithmic rate when a
+    # launch advances two steps on one read and one write)
+    measured = None if traffic is None else traffic / launch_s / 1e9
+    # vector-issue share: a wave64 VALU instruction holds a 16-lane SIMD for
+    # 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+    valu = None if prof is None else prof.get("sq_insts_valu_per_dispatch")
+    valu_frac = None if valu is None else valu * 4 / (1024 * SCLK_HZ * launch_s)
     out = {
         "metric": METRIC,
         "value": round(r16["mlups"], 1),
@@ -412,8 +488,17 @@ def main():
                      "traffic": traffic,
                      "kernel": r16["kernel"], "steps_per_launch": r16["steps_per_launch"],
                      "algorithmic_bytes_per_launch": r16["bytes_per_launch"],
-                     "measured_gbs": None if measured is None else round(measured, 1),
-                     "measured_frac": None if measured is None else round(measured / HBM_PEAK_GBS, 4)},
+                     "launch_us": round(r16["launch_ms"] * 1e3, 3),
+                     "launches_timed": r16["launches"],
+                     "one_step_launch_us": round(r16["one_step_launch_ms"] * 1e3, 3),
+                     "hbm_counted_gbs": None if measured is None else round(measured, 1),
+                     "hbm_counted_frac": None if measured is None else round(measured / HBM_PEAK_GBS, 4),
+                     "valu_issue_frac": None if valu_frac is None else round(valu_frac, 4),
+                     "note": "frac: algorithmic bytes (one read + one write of every population per "
+                             "cell-update) over the live launch time; a two-step launch reads and "
+                             "writes each population once per two steps, so frac can exceed 1. "
+                             "hbm_counted_frac: HBM bytes counted by rocprofv3 per launch over the "
+                             "same time; valu_issue_frac: VALU issue cycles over SIMD cycles"},
         "cpu_baseline": cpu,
         "variant": r16["variant"],
         "d2q36": None if r36 is None else {
@@ -431,6 +516,7 @@ def main():
             "steps_per_launch": r64["steps_per_launch"]},
         "c0_64x64_f64": c0,
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
+        "c2_bounded_flow": c2,
         "batched": bat,
         "finite_volume": fv,
     }

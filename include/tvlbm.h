@@ -160,6 +160,13 @@ int tvlbm_set_variant(tvlbm_ctx *ctx, int32_t variant);
  * this grid: 1 or 2, written to *k (host).  EINVAL for NULL arguments. */
 int tvlbm_steps_per_launch(const tvlbm_ctx *ctx, int32_t *k);
 
+/* Measurement helper, not part of the method: copies `bytes` (a multiple of
+ * 16; src and dst 16-byte aligned, not overlapping) from src to dst on the
+ * stream with a grid-stride 16-byte load/store kernel.  Timed on buffers
+ * larger than the 256 MB Infinity Cache it gives the HBM read + write rate a
+ * streaming kernel reaches on this GPU.  EINVAL on bad arguments. */
+int tvlbm_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 const char *tvlbm_strerror(int code);
 const char *tvlbm_last_error(const tvlbm_ctx *ctx);
 

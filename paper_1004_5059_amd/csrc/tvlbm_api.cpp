@@ -99,6 +99,11 @@ struct tvlbm_ctx {
   double* d_dy = nullptr;
   int32_t* d_rowflag = nullptr;
   std::vector<double> dyh;
+  // fixed-point deviation masses (2^-32 units) of the reference state [0]
+  // and of the last residual check [1], and the grid's area, for the mass
+  // re-imposition of FP32 steady solves
+  unsigned long long* d_mass = nullptr;
+  double* d_area = nullptr;
   std::string err;
 };
 
@@ -382,10 +387,22 @@ static MarchArgs<f32x2> pair_args(const MarchArgs<float>& A) {
   return B;
 }
 
+// Where a march's FP64 block partials, their reduction, the flag and the
+// fixed-point mass tally go.
+struct Sink {
+  double* part;
+  int part_cap;   // blocks the partials hold
+  double* tot;    // reduced totals (4 doubles), or null to skip the reduction
+  int32_t* flag;
+  bool v0;        // launch shape of variant 0 whatever the context's variant
+  unsigned long long* mass = nullptr;  // fixed-point mass tally, or null
+};
+static Sink ctx_sink(tvlbm_ctx* c) { return Sink{c->d_part, c->part_cap, c->d_tot, c->d_flag, false}; }
+
 template <typename R>
 static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
-                     bool want_totals) {
-  const Variant v = kVariants[c->variant].two ? kVariants[0] : kVariants[c->variant];
+                     bool want_totals, const Sink& k) {
+  const Variant v = (k.v0 || kVariants[c->variant].two) ? kVariants[0] : kVariants[c->variant];
   if constexpr (std::is_same<R, float>::value) {
     if (v.pairs && mode == MODE_STEP && pairs_ok(c)) {
       const Geometry g = geometry(c->d.nx / 2, c->d.ny, v);
@@ -418,30 +435,29 @@ static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst
   A.src = (const R*)src;
   A.dst = (R*)dst;
   A.fields = (R*)fields;
-  A.partials = c->d_part;
-  A.flag = c->d_flag;
+  A.partials = k.part;
+  A.flag = k.flag;
+  A.mass = k.mass;
   if (c->rows) {
     A.taps = (const RowTap<R>*)c->d_taps;
     A.inc = (const IncRows<R>*)c->d_inc;
     A.dy = c->d_dy;
     A.rowflag = c->d_rowflag;
   }
-  if (want_totals && g.nblocks > c->part_cap) return fail(c, TVLBM_EINVAL, "partials too small");
+  if (want_totals && g.nblocks > k.part_cap) return fail(c, TVLBM_EINVAL, "partials too small");
   HIPCHK(c, launch_march(c->hl.n, c->comp, mode, A, g.nblocks, c->st));
-  if (want_totals) HIPCHK(c, launch_reduce(c->d_part, g.nblocks, 4, c->d_tot, c->st));
+  if (want_totals && k.tot) HIPCHK(c, launch_reduce(k.part, g.nblocks, 4, k.tot, c->st));
   return TVLBM_OK;
 }
 
-template <typename R>
-static int run_march_any(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst,
-                         void* fields, bool want_totals) {
-  return run_march<R>(c, mode, aux, src, dst, fields, want_totals);
+static int march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
+                 bool want_totals, const Sink& k) {
+  return c->f64 ? run_march<double>(c, mode, aux, src, dst, fields, want_totals, k)
+                : run_march<float>(c, mode, aux, src, dst, fields, want_totals, k);
 }
-
 static int march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst, void* fields,
                  bool want_totals) {
-  return c->f64 ? run_march_any<double>(c, mode, aux, src, dst, fields, want_totals)
-                : run_march_any<float>(c, mode, aux, src, dst, fields, want_totals);
+  return march(c, mode, aux, src, dst, fields, want_totals, ctx_sink(c));
 }
 
 // g^{k+2} from g^k in one launch (two_ok).
@@ -487,6 +503,16 @@ const char* tvlbm_strerror(int code) {
 const char* tvlbm_last_error(const tvlbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int tvlbm_num_variants(void) { return kNumVariants; }
+
+int tvlbm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  if (!src || !dst || bytes < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+    return TVLBM_EINVAL;
+  if (bytes == 0) return TVLBM_OK;
+  const int64_t n16 = bytes / 16;
+  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 8192);
+  return launch_stream_copy(src, dst, n16, nblocks, (hipStream_t)stream) == hipSuccess ? TVLBM_OK
+                                                                                     : TVLBM_EHIP;
+}
 
 int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
   if (!d || !out) return TVLBM_EINVAL;
@@ -539,10 +565,21 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
   if (hipMalloc(&c->d_part, sizeof(double) * 4 * (size_t)cap) != hipSuccess ||
       hipMalloc(&c->d_tot, sizeof(double) * 4) != hipSuccess ||
       hipMalloc(&c->d_flag, sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&c->d_fld[0], fbytes) != hipSuccess || hipMalloc(&c->d_fld[1], fbytes) != hipSuccess) {
+      hipMalloc(&c->d_fld[0], fbytes) != hipSuccess || hipMalloc(&c->d_fld[1], fbytes) != hipSuccess ||
+      hipMalloc(&c->d_mass, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_area, sizeof(double)) != hipSuccess) {
     hipFree(c->d_part); hipFree(c->d_tot); hipFree(c->d_flag);
-    hipFree(c->d_fld[0]); hipFree(c->d_fld[1]);
+    hipFree(c->d_fld[0]); hipFree(c->d_fld[1]); hipFree(c->d_mass); hipFree(c->d_area);
     return bad(TVLBM_ENOMEM, "scratch");
+  }
+  {
+    double area = 0.0;
+    for (int j = 0; j < d->ny; ++j) area += c->dyh.empty() ? 1.0 : c->dyh[j];
+    area *= d->nx;
+    if (hipMemcpy(c->d_area, &area, sizeof area, hipMemcpyHostToDevice) != hipSuccess) {
+      tvlbm_destroy(c);
+      return TVLBM_EHIP;
+    }
   }
   if (hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->st) != hipSuccess) {
     tvlbm_destroy(c);
@@ -580,6 +617,8 @@ int tvlbm_destroy(tvlbm_ctx* c) {
   hipFree(c->d_inc);
   hipFree(c->d_dy);
   hipFree(c->d_rowflag);
+  hipFree(c->d_mass);
+  hipFree(c->d_area);
   delete c;
   return TVLBM_OK;
 }
@@ -646,10 +685,13 @@ int tvlbm_step(tvlbm_ctx* c, int32_t nsteps) {
 }
 
 // f^k = S(g^{k-1}) from buf[cur^1]; at k = 0 buf[cur^1] holds f^0 itself.
-static int aux_from_state(tvlbm_ctx* c, int aux, void* dst, void* fields, bool totals) {
+static int aux_from_state(tvlbm_ctx* c, int aux, void* dst, void* fields, bool totals,
+                          unsigned long long* mass = nullptr) {
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
   if (c->step == 0) aux |= AUX_IDENTITY;
-  return march(c, MODE_AUX, aux, c->buf[c->cur ^ 1], dst, fields, totals);
+  Sink k = ctx_sink(c);
+  k.mass = mass;
+  return march(c, MODE_AUX, aux, c->buf[c->cur ^ 1], dst, fields, totals, k);
 }
 
 int tvlbm_populations(tvlbm_ctx* c, void* f_out) {
@@ -693,7 +735,8 @@ int tvlbm_moments(tvlbm_ctx* c, void* rho, void* ux, void* uy, void* T, double t
 int tvlbm_residual(tvlbm_ctx* c, double* r) {
   if (!c || !r) return fail(c, TVLBM_EINVAL, "null");
   const int slot = c->fld_cur ^ 1;
-  int rc = aux_from_state(c, AUX_FIELDS, nullptr, c->d_fld[slot], true);
+  HIPCHK(c, launch_fill_i32((int32_t*)(c->d_mass + 1), 2, 0, c->st));
+  int rc = aux_from_state(c, AUX_FIELDS, nullptr, c->d_fld[slot], true, c->d_mass + 1);
   if (rc) return rc;
   double res = std::numeric_limits<double>::infinity();
   const int64_t nval = (int64_t)4 * c->d.nx * c->d.ny;
@@ -727,12 +770,29 @@ int tvlbm_residual(tvlbm_ctx* c, double* r) {
   return TVLBM_OK;
 }
 
+// FP32 storage: the collision's rounding (lattice constants rounded to
+// FP32) shifts the mass by ~1e-9 of it per step where T != 1, which adds up
+// over a steady solve of 10^5 steps.  At every residual check the deficit
+// against the solve's starting mass, both tallied exactly in fixed point, is
+// added back to the post-collision state as delta w_l per cell.  FP64
+// conserves to round-off and is left untouched.
+static int reimpose_mass(tvlbm_ctx* c) {
+  if (c->f64) return TVLBM_OK;
+  Inst<float> P = c->instf;
+  P.id = 0;
+  HIPCHK(c, launch_mass_fix((float*)c->buf[c->cur], nullptr, P, nullptr, c->d_mass, c->d_mass + 1,
+                            c->d_area, c->latf, c->hl.q, 1, c->st));
+  return TVLBM_OK;
+}
+
 int tvlbm_solve(tvlbm_ctx* c, int64_t max_steps, double tol, int32_t k_interval,
                 int64_t* steps_done, double* r_final) {
   if (!c || k_interval < 1 || max_steps < 0) return fail(c, TVLBM_EINVAL, "solve args");
   double r = std::numeric_limits<double>::infinity();
   int rc = tvlbm_residual(c, &r);  // snapshot of the starting state
   if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->d_mass, c->d_mass + 1, sizeof(unsigned long long),
+                           hipMemcpyDeviceToDevice, c->st));
   const int64_t start = c->step;
   while (c->step - start < max_steps) {
     const int32_t k = (int32_t)std::min<int64_t>(k_interval, max_steps - (c->step - start));
@@ -741,6 +801,8 @@ int tvlbm_solve(tvlbm_ctx* c, int64_t max_steps, double tol, int32_t k_interval,
     rc = tvlbm_residual(c, &r);
     if (rc) return rc;
     if (r < tol) break;
+    rc = reimpose_mass(c);
+    if (rc) return rc;
   }
   if (steps_done) *steps_done = c->step - start;
   if (r_final) *r_final = r;
@@ -883,6 +945,11 @@ struct tvlbm_batch {
   int32_t* d_flag = nullptr;
   void* d_fields = nullptr;
   void* d_prev = nullptr;
+  // fixed-point deviation masses per instance: at the run's start and at the
+  // last check; instance areas (FP32 mass re-imposition, as tvlbm_solve)
+  unsigned long long* d_mass0 = nullptr;
+  unsigned long long* d_mass = nullptr;
+  double* d_area = nullptr;
   int32_t* h_remaining = nullptr;  // pinned
   struct Shape { int max_nx, width, rows; };
   std::vector<Shape> shapes;
@@ -1028,7 +1095,7 @@ int batch_blocks(int n_items) {
 
 template <typename R>
 int batch_march(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
-                const Work* work, int nblocks) {
+                const Work* work, int nblocks, unsigned long long* mass) {
   MarchArgs<R> A;
   std::memset(&A, 0, sizeof A);
   A.lat = std::is_same<R, float>::value ? *(Lat<R>*)(void*)&b->latf : *(Lat<R>*)(void*)&b->latd;
@@ -1040,14 +1107,15 @@ int batch_march(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, c
   A.dst = (R*)dst;
   A.fields = (R*)b->d_fields;
   A.flag = b->d_flag;
+  A.mass = mass;
   BHIP(b, launch_march_batch(b->hl.n, b->comp, mode, b->prefetch != 0, A, nblocks, b->st));
   return TVLBM_OK;
 }
 
 int bmarch(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const int32_t* nwork,
-           const Work* work, int nblocks) {
-  return b->f64 ? batch_march<double>(b, mode, aux, src, dst, nwork, work, nblocks)
-                : batch_march<float>(b, mode, aux, src, dst, nwork, work, nblocks);
+           const Work* work, int nblocks, unsigned long long* mass = nullptr) {
+  return b->f64 ? batch_march<double>(b, mode, aux, src, dst, nwork, work, nblocks, mass)
+                : batch_march<float>(b, mode, aux, src, dst, nwork, work, nblocks, mass);
 }
 
 // Rebuild the live work list from the active instances' items of the bulk
@@ -1084,13 +1152,24 @@ int batch_resid(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
 // post-collision state is in buf[0] (K is even).
 int enqueue_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps, bool tail) {
   const int nblocks = batch_blocks(tail ? b->n_items_tail : b->n_items);
+  const int n = (int)b->inst.size();
+  BHIP(b, launch_fill_i32((int32_t*)b->d_mass, 2 * n, 0, b->st));
   for (int s = 0; s < K; ++s) {
     const int mode = (s == K - 1) ? MODE_CHECK : MODE_STEP;
-    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work, nblocks);
+    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work, nblocks,
+                    mode == MODE_CHECK ? b->d_mass : nullptr);
     if (rc) return rc;
   }
   int rc = b->f64 ? batch_resid<double>(b, K, tol, max_steps) : batch_resid<float>(b, K, tol, max_steps);
   if (rc) return rc;
+  if (!b->f64) {
+    // FP32: the instances that go on get their starting mass back (see
+    // reimpose_mass); their post-collision state is in buf[0] (K even)
+    Inst<float> none;
+    std::memset(&none, 0, sizeof none);
+    BHIP(b, launch_mass_fix((float*)b->buf[0], (const Inst<float>*)b->d_insts, none, b->d_active,
+                            b->d_mass0, b->d_mass, b->d_area, b->latf, b->hl.q, n, b->st));
+  }
   return compact(b, tail);
 }
 
@@ -1135,6 +1214,7 @@ int tvlbm_batch_destroy(tvlbm_batch* b) {
   hipFree(b->d_rpart); hipFree(b->d_nwork); hipFree(b->d_ntotal); hipFree(b->d_remaining);
   hipFree(b->d_active); hipFree(b->d_have_prev); hipFree(b->d_steps); hipFree(b->d_resid);
   hipFree(b->d_flag); hipFree(b->d_fields); hipFree(b->d_prev);
+  hipFree(b->d_mass0); hipFree(b->d_mass); hipFree(b->d_area);
   if (b->h_remaining) hipHostFree(b->h_remaining);
   delete b;
   return TVLBM_OK;
@@ -1196,9 +1276,15 @@ int tvlbm_batch_init(const tvlbm_batch_desc* d, tvlbm_batch** out) {
             hipMalloc(&b->d_flag, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_fields, esz * b->field_elems) == hipSuccess &&
             hipMalloc(&b->d_prev, esz * b->field_elems) == hipSuccess &&
+            hipMalloc(&b->d_mass0, sizeof(unsigned long long) * n) == hipSuccess &&
+            hipMalloc(&b->d_mass, sizeof(unsigned long long) * n) == hipSuccess &&
+            hipMalloc(&b->d_area, sizeof(double) * n) == hipSuccess &&
             hipHostMalloc((void**)&b->h_remaining, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (!ok) { tvlbm_batch_destroy(b); return TVLBM_ENOMEM; }
-  if (hipMemcpy(b->d_insts, hinst.data(), isz * n, hipMemcpyHostToDevice) != hipSuccess) {
+  std::vector<double> area(n);
+  for (int k = 0; k < n; ++k) area[k] = (double)b->inst[k].nx * b->inst[k].ny;
+  if (hipMemcpy(b->d_insts, hinst.data(), isz * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_area, area.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
     tvlbm_batch_destroy(b);
     return TVLBM_EHIP;
   }
@@ -1295,7 +1381,9 @@ int tvlbm_batch_run(tvlbm_batch* b, int64_t max_steps, double tol, int32_t K, in
   // residual (as the single-instance solve does)
   {
     const int aux = AUX_FIELDS | (b->stepped ? 0 : AUX_IDENTITY);
-    int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all, batch_blocks(b->n_items));
+    BHIP(b, launch_fill_i32((int32_t*)b->d_mass0, 2 * n, 0, b->st));
+    int rc = bmarch(b, MODE_AUX, aux, b->buf[1], nullptr, b->d_ntotal, b->d_all, batch_blocks(b->n_items),
+                    b->d_mass0);
     if (rc) return rc;
     const size_t esz = b->f64 ? 8 : 4;
     BHIP(b, hipMemcpyAsync(b->d_prev, b->d_fields, esz * b->field_elems, hipMemcpyDeviceToDevice, b->st));

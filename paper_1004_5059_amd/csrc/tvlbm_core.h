@@ -152,7 +152,13 @@ struct MarchArgs {
   const IncRows<R>* inc;  // non-uniform rows with walls: [n]
   const double* dy;       // non-uniform rows: [ny] heights
   const int32_t* rowflag; // bit 0: row pulls the bottom ghost, bit 1: the top
+  unsigned long long* mass;  // CHECK / AUX_FIELDS: fixed-point deviation mass
+                             // per instance (index Inst::id / work item), or null
 };
+
+// Fixed-point unit of the exact, order-independent mass tallies:
+// sum_l (f_l - w_l) dy per cell rounded to multiples of 2^-32.
+constexpr double MASS_FP_SCALE = 4294967296.0;
 
 // Fused multiply-add in the working precision (the double builtin would
 // promote float operands).
@@ -398,6 +404,25 @@ __device__ __forceinline__ R eq_dev(const Lat<R>& L, const EqNodes<R, N>& E, int
 template <typename R>
 __device__ __forceinline__ R bgk(R d, R oww_l, R omo, R e) {
   return fmaR(oww_l, e, omo * d);
+}
+
+// Equilibrium and BGK of one cell, in place: d[l] <- C(d)[l], given the
+// cell's fields F.
+template <typename R, int N, int ORD>
+__device__ __forceinline__ void bgk_cell(const Lat<R>& L, const Inst<R>& P, const Fields<R>& F,
+                                         R (&d)[N * N]) {
+  EqNodes<R, N> E;
+  eq_nodes<R, N, ORD>(L, F, E);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    R Fa, Ka, Na;
+    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int l = a * N + b;
+      d[l] = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
+    }
+  }
 }
 
 }  // namespace tvlbm

@@ -101,7 +101,7 @@ __device__ __forceinline__ R ghost_pull(const Lat<R>& L, int a, R kap, R phi, R 
 template <typename R, int N, int ORD, bool COMP, int MODE>
 __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& P, rsrc_t dst,
                                           const R (&d)[N * N], int j, int i, bool active,
-                                          double dyj, double (&tot)[4], int& bad) {
+                                          double dyj, double (&tot)[5], int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
@@ -122,7 +122,7 @@ __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& 
         fo[2 * fp] = F.uy;
         fo[3 * fp] = T;
       }
-      double m = 0.0, px = 0.0, py = 0.0, e = 0.0;
+      double m = 0.0, px = 0.0, py = 0.0, e = 0.0, dm = 0.0;
 #pragma unroll
       for (int a = 0; a < N; ++a) {
 #pragma unroll
@@ -130,12 +130,16 @@ __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& 
           const int l = a * N + b;
           const double fa = L.wd[l] + (double)d[l];
           m += fa;
+          dm += (double)d[l];
           px += L.xd[a] * fa;
           py += L.xd[b] * fa;
           e += 0.5 * (L.xd[a] * L.xd[a] + L.xd[b] * L.xd[b]) * fa;
         }
       }
       tot[0] += dyj * m; tot[1] += dyj * px; tot[2] += dyj * py; tot[3] += dyj * e;
+      // the cell's deviation mass in fixed point (an integer, held exactly
+      // in the double while |sum| < 2^53), for order-independent totals
+      tot[4] += (double)__double2ll_rn(dyj * dm * MASS_FP_SCALE);
     }
   }
 
@@ -151,23 +155,18 @@ __device__ __forceinline__ void cell_tail(const MarchArgs<R>& A, const Inst<R>& 
     if (!(A.aux & AUX_POST)) return;
   }
 
-  EqNodes<R, N> E;
-  eq_nodes<R, N, ORD>(L, F, E);
+  R g[Q];
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    R Fa, Ka, Na;
-    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
+  for (int l = 0; l < Q; ++l) g[l] = d[l];
+  bgk_cell<R, N, ORD>(L, P, F, g);
+  if (active) {
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      const R g = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
-      if (active) {
-        if constexpr (MODE == MODE_AUX) {
-          const int64_t op = (int64_t)nx * ny;
-          A.dst[l * op + (int64_t)j * nx + i] = g + L.w[l];
-        } else {
-          bst(dst, (uint32_t)j * (uint32_t)P.ld + (uint32_t)i, (uint32_t)(l * P.plane), g);
-        }
+    for (int l = 0; l < Q; ++l) {
+      if constexpr (MODE == MODE_AUX) {
+        const int64_t op = (int64_t)nx * ny;
+        A.dst[l * op + (int64_t)j * nx + i] = g[l] + L.w[l];
+      } else {
+        bst(dst, (uint32_t)j * (uint32_t)P.ld + (uint32_t)i, (uint32_t)(l * P.plane), g[l]);
       }
     }
   }
@@ -195,7 +194,7 @@ template <typename R, int N, int ORD, bool COMP, int MODE, int DIR, bool GHOST>
 __device__ __forceinline__ void march_row(const MarchArgs<R>& A, const Inst<R>& P,
                                           rsrc_t s, rsrc_t dst, R (&hp)[N * N], int j,
                                           int i, int ic, int im, int ip, bool active,
-                                          bool ident, double (&tot)[4], int& bad) {
+                                          bool ident, double (&tot)[5], int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
@@ -296,7 +295,7 @@ __device__ __forceinline__ void pull_row(const Lat<R>& L, const R (&c)[N * N], c
 // One lane's segment of rows [j0, j1), marched in direction DIR.
 template <typename R, int N, int ORD, bool COMP, int MODE, int DIR, bool PF>
 __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& P, int i,
-                                          bool active, int j0, int j1, double (&tot)[4],
+                                          bool active, int j0, int j1, double (&tot)[5],
                                           int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
@@ -380,7 +379,7 @@ __device__ __forceinline__ void march_dir(const MarchArgs<R>& A, const Inst<R>& 
 // both at their end -- and the second read hits in L2.
 template <typename R, int N, int ORD, bool COMP, int MODE, bool PF>
 __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>& P, int i,
-                                           bool active, int j0, int j1, int group, double (&tot)[4],
+                                           bool active, int j0, int j1, int group, double (&tot)[5],
                                            int& bad) {
   if (group & 1)
     march_dir<R, N, ORD, COMP, MODE, -1, PF>(A, P, i, active, j0, j1, tot, bad);
@@ -388,8 +387,17 @@ __device__ __forceinline__ void march_lane(const MarchArgs<R>& A, const Inst<R>&
     march_dir<R, N, ORD, COMP, MODE, +1, PF>(A, P, i, active, j0, j1, tot, bad);
 }
 
+// Wave sum of the fixed-point mass tally tot[4], added to *slot by lane 0
+// (integer addition: exact and independent of the order of the waves).
+__device__ __forceinline__ void wave_mass(double t4, unsigned long long* slot) {
+  long long v = (long long)t4;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(slot, (unsigned long long)v);
+}
+
 template <int MODE>
-__device__ __forceinline__ void block_totals(const double (&tot)[4], int bad, double* partials,
+__device__ __forceinline__ void block_totals(const double (&tot)[5], int bad, double* partials,
                                              int32_t* flag) {
   __shared__ double sh[4][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
   const int spb = 4 * spw;      // segments per workgroup
   const int nb = gridDim.x;     // multiple of 8
   const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int bad = 0;
   if (t < A.n_tiles) {
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
@@ -433,7 +441,10 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<R> A) {
       march_lane<R, N, ORD, COMP, MODE, PF>(A, A.inst, i, i < A.inst.nx, j0, j1, group, tot, bad);
   }
   if constexpr (MODE != MODE_STEP) {
-    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
+    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) {
+      block_totals<MODE>(tot, bad, A.partials, A.flag);
+      if (A.mass) wave_mass(tot[4], A.mass);
+    }
   }
 }
 
@@ -474,18 +485,9 @@ __device__ __forceinline__ void collide_regs(const Lat<R>& L, const Inst<R>& P,
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
-  EqNodes<R, N> E;
-  eq_nodes<R, N, ORD>(L, F, E);
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    R Fa, Ka, Na;
-    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      g[l] = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
-    }
-  }
+  for (int l = 0; l < N * N; ++l) g[l] = d[l];
+  bgk_cell<R, N, ORD>(L, P, F, g);
 }
 
 __device__ __forceinline__ int wrap_row(int j, int ny) {
@@ -668,7 +670,7 @@ __device__ __forceinline__ R wall_mass_rows(const Lat<R>& L, const IncRows<R>* _
 // One cell of a grid with tabulated (non-uniform) rows.
 template <typename R, int N, int ORD, bool COMP, int MODE>
 __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& P, rsrc_t s,
-                                          rsrc_t dst, int k, int i, bool active, double (&tot)[4],
+                                          rsrc_t dst, int k, int i, bool active, double (&tot)[5],
                                           int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
@@ -729,7 +731,7 @@ __global__ __launch_bounds__(256) void k_rows(const MarchArgs<R> A) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nb = gridDim.x;
   const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int bad = 0;
   const Inst<R>& P = A.inst;
   if (t < A.n_tiles) {
@@ -744,7 +746,10 @@ __global__ __launch_bounds__(256) void k_rows(const MarchArgs<R> A) {
     }
   }
   if constexpr (MODE != MODE_STEP) {
-    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) block_totals<MODE>(tot, bad, A.partials, A.flag);
+    if (MODE == MODE_CHECK || (A.aux & AUX_FIELDS)) {
+      block_totals<MODE>(tot, bad, A.partials, A.flag);
+      if (A.mass) wave_mass(tot[4], A.mass);
+    }
   }
 }
 
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_work = *A.n_work;
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int bad = 0;
   // Workgroups go round-robin to the 8 XCDs.  Split the live list into 8
   // equal contiguous ranges, one per XCD, so that adjacent segments of a
@@ -783,6 +788,12 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
     const int j1 = min(j0 + rows, P.ny);
     const int group = it.seg0 / (64 / W);
     if (j0 < P.ny) march_lane<R, N, ORD, COMP, MODE, PF>(A, P, i, i < P.nx, j0, j1, group, tot, bad);
+    if constexpr (MODE != MODE_STEP) {
+      if (A.mass && (MODE == MODE_CHECK || (A.aux & AUX_FIELDS))) {
+        wave_mass(tot[4], A.mass + it.inst);  // the item's instance
+        tot[4] = 0.0;
+      }
+    }
   }
   if constexpr (MODE != MODE_STEP) {
     if (bad) A.flag[0] = 1;
@@ -927,17 +938,36 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs<R> A) {
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
-  EqNodes<R, N> E;
-  eq_nodes<R, N, ORD>(L, F, E);
+  bgk_cell<R, N, ORD>(L, P, F, d);
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    R Fa, Ka, Na;
-    eq_anode<R, N, ORD>(L, E, a, Fa, Ka, Na);
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int l = a * N + b;
-      A.g0[o + l * P.plane] = bgk(d[l], P.oww[l], P.omo, eq_dev<R, N, ORD>(L, E, a, b, Fa, Ka, Na));
-    }
+  for (int l = 0; l < Q; ++l) A.g0[o + l * P.plane] = d[l];
+}
+
+// ------------------------------------------------------ mass re-imposition --
+// Adds delta w_l to every population of an instance's post-collision state,
+// delta = (M0 - M) / area from the fixed-point deviation masses of the
+// reference state (ref) and of the last check (cur): the deficit re-enters
+// as a uniform density increment at rest (zero momentum).  Batched runs
+// (active != null) touch active instances only; RESID_SLICES workgroups per
+// instance stride over its cells.
+template <typename R>
+__global__ __launch_bounds__(256) void k_mass_fix(R* __restrict__ g, const Inst<R>* __restrict__ insts,
+                                                  Inst<R> single, const int32_t* __restrict__ active,
+                                                  const unsigned long long* __restrict__ ref,
+                                                  const unsigned long long* __restrict__ cur,
+                                                  const double* __restrict__ area, Lat<R> L, int q) {
+  const int b = blockIdx.x / RESID_SLICES, sl = blockIdx.x % RESID_SLICES;
+  if (active && !active[b]) return;
+  const Inst<R>& P = insts ? insts[b] : single;
+  const long long dmi = (long long)(ref[b] - cur[b]);
+  if (dmi == 0) return;
+  const R delta = (R)((double)dmi / MASS_FP_SCALE / area[b]);
+  const int64_t n = (int64_t)P.nx * P.ny;
+  const int64_t k0 = n * sl / RESID_SLICES, k1 = n * (sl + 1) / RESID_SLICES;
+  for (int64_t c = k0 + threadIdx.x; c < k1; c += 256) {
+    const int64_t j = c / P.nx, i = c % P.nx;
+    R* p = g + P.off + j * P.ld + i;
+    for (int l = 0; l < q; ++l) p[l * P.plane] = fmaR(L.w[l], delta, p[l * P.plane]);
   }
 }
 
@@ -958,6 +988,29 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
     if (threadIdx.x == 0) out[c] = sh[0];
     __syncthreads();
   }
+}
+
+// p[0..n) = v (a kernel rather than a memset, so that it may sit in a
+// captured graph)
+__global__ __launch_bounds__(64) void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  for (int k = threadIdx.x; k < n; k += 64) p[k] = v;
+}
+
+// Streaming copy of n 16-byte elements (grid-stride, four in flight per
+// lane): the achievable HBM read + write rate on buffers larger than the
+// Infinity Cache, the practical ceiling the step kernels are compared with.
+__global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ src,
+                                                     float4* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; k + 3 * stride < n; k += 4 * stride) {
+    const float4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+    dst[k] = a;
+    dst[k + stride] = b;
+    dst[k + 2 * stride] = c;
+    dst[k + 3 * stride] = d;
+  }
+  for (; k < n; k += stride) dst[k] = src[k];
 }
 
 // per-block partial sums of (q - qp)^2 and q^2 over n values
@@ -1145,6 +1198,38 @@ hipError_t launch_batch_compact(const int32_t* active, const int32_t* item_start
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_batch_compact, dim3(n_inst), dim3(256), 0, st, active, item_start, all, work,
                      n_work, remaining, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_copy, dim3(nblocks), dim3(256), 0, st, (const float4*)src, (float4*)dst,
+                     n16);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t mass_fix_impl(R* g, const Inst<R>* insts, const Inst<R>& single, const int32_t* active,
+                                const unsigned long long* ref, const unsigned long long* cur,
+                                const double* area, const Lat<R>& L, int q, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_mass_fix<R>, dim3(n_inst * RESID_SLICES), dim3(256), 0, st, g, insts, single, active,
+                     ref, cur, area, L, q);
+  return hipGetLastError();
+}
+hipError_t launch_mass_fix(float* g, const Inst<float>* insts, const Inst<float>& single,
+                           const int32_t* active, const unsigned long long* ref,
+                           const unsigned long long* cur, const double* area, const Lat<float>& L,
+                           int q, int n_inst, hipStream_t st) {
+  return mass_fix_impl(g, insts, single, active, ref, cur, area, L, q, n_inst, st);
+}
+hipError_t launch_mass_fix(double* g, const Inst<double>* insts, const Inst<double>& single,
+                           const int32_t* active, const unsigned long long* ref,
+                           const unsigned long long* cur, const double* area, const Lat<double>& L,
+                           int q, int n_inst, hipStream_t st) {
+  return mass_fix_impl(g, insts, single, active, ref, cur, area, L, q, n_inst, st);
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -65,6 +65,21 @@ hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, 
 hipError_t launch_init(int n, bool comp, const InitArgs<float>& A, hipStream_t st);
 hipError_t launch_init(int n, bool comp, const InitArgs<double>& A, hipStream_t st);
 hipError_t launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t st);
+// g += delta_b w_l for every cell of instance b (n_inst instances: insts[b],
+// or `single` when insts is null), delta_b = (ref[b] - cur[b]) 2^-32 / area[b];
+// instances with active[b] == 0 are skipped (active may be null).
+hipError_t launch_mass_fix(float* g, const Inst<float>* insts, const Inst<float>& single,
+                           const int32_t* active, const unsigned long long* ref,
+                           const unsigned long long* cur, const double* area, const Lat<float>& L,
+                           int q, int n_inst, hipStream_t st);
+hipError_t launch_mass_fix(double* g, const Inst<double>* insts, const Inst<double>& single,
+                           const int32_t* active, const unsigned long long* ref,
+                           const unsigned long long* cur, const double* area, const Lat<double>& L,
+                           int q, int n_inst, hipStream_t st);
+// dst = src, n16 elements of 16 bytes, grid-stride over nblocks workgroups.
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, int nblocks, hipStream_t st);
+// p[0..n) = v on the stream (n <= 64 is one wavefront's pass).
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
 hipError_t launch_resid(const float* q, const float* qp, int64_t n, double* part, int nblk,
                         hipStream_t st);
 hipError_t launch_resid(const double* q, const double* qp, int64_t n, double* part, int nblk,

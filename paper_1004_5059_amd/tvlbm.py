@@ -158,6 +158,7 @@ def lib():
         "tvlbm_save": [_vp, ctypes.c_char_p],
         "tvlbm_load": [_vp, ctypes.c_char_p],
         "tvlbm_num_variants": [],
+        "tvlbm_stream_copy": [_vp, _vp, ctypes.c_int64, _vp],
         "tvlbm_set_variant": [_vp, ctypes.c_int32],
         "tvlbm_steps_per_launch": [_vp, ctypes.POINTER(ctypes.c_int32)],
         "tvlbm_strerror": [ctypes.c_int],
@@ -215,6 +216,13 @@ def tvlbm_strerror(code: int) -> str:
 
 def tvlbm_last_error(ctx) -> str:
     return lib().tvlbm_last_error(ctx).decode()
+
+
+def tvlbm_stream_copy(src, dst, nbytes: int, stream=None):
+    """Bandwidth probe: dst[:nbytes] = src[:nbytes] with the library's
+    16-byte streaming copy kernel, on the given stream (or the null stream)."""
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib().tvlbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), st))
 
 
 def tvlbm_num_variants() -> int:

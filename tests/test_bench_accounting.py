@@ -12,29 +12,30 @@ import bench  # noqa: E402
 
 
 def _write(tmp_path, **kw):
-    d = {"kernel_hash": bench._kernel_hash(), "steps_per_launch": 2,
-         "hbm_bytes_per_launch": 123456789}
+    d = {"kernel_hash": bench._kernel_hash(), "steps_per_launch": 2, "variant": 22,
+         "hbm_bytes_per_launch": 123456789, "sq_insts_valu_per_dispatch": 1000}
     d.update(kw)
     (tmp_path / "profiles").mkdir(exist_ok=True)
     (tmp_path / "profiles" / "fused_step_d2q16_1024_counters.json").write_text(json.dumps(d))
 
 
-def test_traffic_needs_the_same_source_and_launch_kind(tmp_path, monkeypatch):
+def test_counters_need_the_same_source_launch_kind_and_variant(tmp_path, monkeypatch):
     h = bench._kernel_hash()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "_kernel_hash", lambda: h)
     _write(tmp_path)
-    assert bench.traffic_from_profile(2) == 123456789
-    assert bench.traffic_from_profile(1) is None
+    assert bench.counters_from_profile(2, 22)["hbm_bytes_per_launch"] == 123456789
+    assert bench.counters_from_profile(1, 22) is None
+    assert bench.counters_from_profile(2, 21) is None
     _write(tmp_path, kernel_hash="0" * 16)
-    assert bench.traffic_from_profile(2) is None
+    assert bench.counters_from_profile(2, 22) is None
     _write(tmp_path, steps_per_launch=None)
-    assert bench.traffic_from_profile(2) is None
+    assert bench.counters_from_profile(2, 22) is None
 
 
-def test_traffic_without_a_counter_file(tmp_path, monkeypatch):
+def test_counters_without_a_counter_file(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.traffic_from_profile(1) is None
+    assert bench.counters_from_profile(1, 0) is None
 
 
 def test_committed_counter_file_is_complete():
