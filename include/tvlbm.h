@@ -114,6 +114,31 @@ int tvlbm_post_collision(tvlbm_ctx *ctx, void *g_out);
 int tvlbm_moments(tvlbm_ctx *ctx, void *rho, void *ux, void *uy, void *T,
                   double totals[4]);
 
+/* For callers that cannot allocate device memory (code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the
+ * moments of tvlbm_moments without any allocation and without a host
+ * synchronisation.  Enqueues on the context's stream only kernels (no
+ * memset, no copy), so the call can be captured.
+ *   fields: device [4][ny][nx] in the context's dtype (rho, ux, uy, T), or
+ *           NULL;
+ *   totals: device double[4] (M, Px, Py, E in FP64, as tvlbm_moments), or
+ *           NULL;
+ *   flag:   device int32, set to 1 if any cell has rho <= 0, T <= 0 or a
+ *           non-finite moment and to 0 otherwise, or NULL.
+ * Outputs are caller-owned and valid once the stream reaches the call.
+ * The per-block partial sums live in a static 2 MiB device array of the
+ * library, one per GPU, resolved at tvlbm_init: grids needing more than
+ * 65536 partial blocks (more than 16,777,216 cells with uniform rows,
+ * 4,194,304 with non-uniform rows) are rejected with EINVAL before anything
+ * is enqueued.  Calls that overlap on one GPU (several contexts or streams
+ * at once) race on that array.  EINVAL also if the current device is not the
+ * context's, or the populations are not set.  A captured call reads the
+ * buffer that holds the state when it is captured (the two buffers swap at
+ * every launch of tvlbm_step): replay it when the context is back in that
+ * buffer, e.g. in a graph that also holds the steps, advancing an even
+ * number of launches. */
+int tvlbm_moments_static(tvlbm_ctx *ctx, void *fields, double *totals, int32_t *flag);
+
 /* Residual r = ||q^k - q^m||_2 / ((k - m) ||q^k||_2), q = stacked
  * (rho, ux, uy, T) over all cells, where m is the step of the previous call
  * (r = +inf on the first call or if no step was taken).  Synchronises. */

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -99,6 +100,7 @@ struct tvlbm_ctx {
   double* d_dy = nullptr;
   int32_t* d_rowflag = nullptr;
   std::vector<double> dyh;
+  int dev = 0;          // device current at tvlbm_init
   // fixed-point deviation masses (2^-32 units) of the reference state [0]
   // and of the last residual check [1], and the grid's area, for the mass
   // re-imposition of FP32 steady solves
@@ -388,7 +390,9 @@ static MarchArgs<f32x2> pair_args(const MarchArgs<float>& A) {
 }
 
 // Where a march's FP64 block partials, their reduction, the flag and the
-// fixed-point mass tally go.
+// fixed-point mass tally go: the context's own buffers, or
+// (tvlbm_moments_static) the library's static scratch and the caller's
+// outputs.
 struct Sink {
   double* part;
   int part_cap;   // blocks the partials hold
@@ -484,6 +488,47 @@ static int march2(tvlbm_ctx* c, const void* src, void* dst) {
 
 static size_t esize(const tvlbm_ctx* c) { return c->f64 ? 8 : 4; }
 
+// ---------------------------------------------------------------------------
+// Static scratch of tvlbm_moments_static: the per-block FP64 partials of the
+// totals (SCRATCH_BLOCKS x 4 doubles, 2 MiB) and a flag word, in a
+// file-scope device array, so that the call allocates nothing.  Each device
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name is only a stand-in for the device symbol: tvlbm_init
+// resolves the array's address on the current device once, with
+// hipGetSymbolAddress, and the entry point passes that address (never the
+// name) to its kernels.
+constexpr int SCRATCH_BLOCKS = 65536;
+constexpr int SCRATCH_FLAG = SCRATCH_BLOCKS * 4;  // index of the flag word (as a double slot)
+static __device__ __align__(256) double scratch[SCRATCH_BLOCKS * 4 + 32];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Address of `scratch` on the current device (resolved once per device).
+static int resolve_scratch(int* dev_out, std::string* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = "hipGetDevice failed";
+    return TVLBM_EHIP;
+  }
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+    *err = "device ordinal beyond the static scratch table";
+    return TVLBM_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return TVLBM_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *dev_out = dev;
+  return TVLBM_OK;
+}
+
 extern "C" {
 
 const char* tvlbm_strerror(int code) {
@@ -550,6 +595,11 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
   c->st = (hipStream_t)d->stream;
   c->buf[0] = d->f_a;
   c->buf[1] = d->f_b;
+  {
+    std::string e;
+    const int rc = resolve_scratch(&c->dev, &e);
+    if (rc != TVLBM_OK) return bad(rc, e.c_str());
+  }
   const int walls = d->y_bc == TVLBM_BC_DIFFUSE_WALLS;
   fill_lat(c->hl, c->latf);
   fill_lat(c->hl, c->latd);
@@ -730,6 +780,26 @@ int tvlbm_moments(tvlbm_ctx* c, void* rho, void* ux, void* uy, void* T, double t
   if (totals) std::memcpy(totals, t, sizeof t);
   if (flag) return fail(c, TVLBM_ENONFINITE, "rho <= 0, T <= 0 or non-finite moment");
   return TVLBM_OK;
+}
+
+int tvlbm_moments_static(tvlbm_ctx* c, void* fields, double* totals, int32_t* flag) {
+  if (!c) return TVLBM_EINVAL;
+  if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->dev)
+    return fail(c, TVLBM_EINVAL, "the context's device is not the current device");
+  double* base = (double*)g_scratch_ptr[dev];
+  if (!base) return fail(c, TVLBM_EHIP, "static scratch not resolved on this device");
+  const Geometry g = c->rows ? geometry_rows(c->d.nx, c->d.ny) : geometry(c->d.nx, c->d.ny, kVariants[0]);
+  if (g.nblocks > SCRATCH_BLOCKS)
+    return fail(c, TVLBM_EINVAL,
+                "grid too large for tvlbm_moments_static: " + std::to_string(g.nblocks) +
+                    " partial blocks, the static scratch holds " + std::to_string(SCRATCH_BLOCKS));
+  int32_t* fl = flag ? flag : (int32_t*)(base + SCRATCH_FLAG);
+  HIPCHK(c, launch_fill_i32(fl, 1, 0, c->st));
+  const Sink k{base, SCRATCH_BLOCKS, totals, fl, true};
+  const int aux = AUX_FIELDS | (c->step == 0 ? AUX_IDENTITY : 0);
+  return march(c, MODE_AUX, aux, c->buf[c->cur ^ 1], nullptr, fields, true, k);
 }
 
 int tvlbm_residual(tvlbm_ctx* c, double* r) {

@@ -149,6 +149,7 @@ def lib():
         "tvlbm_populations": [_vp, _vp],
         "tvlbm_post_collision": [_vp, _vp],
         "tvlbm_moments": [_vp, _vp, _vp, _vp, _vp, _dp],
+        "tvlbm_moments_static": [_vp, _vp, _vp, _vp],
         "tvlbm_residual": [_vp, _dp],
         "tvlbm_solve": [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _i64p, _dp],
         "tvlbm_step_count": [_vp, _i64p],
@@ -265,6 +266,12 @@ def tvlbm_moments(ctx, rho=None, ux=None, uy=None, T=None, check=True):
     if check:
         _check(rc, ctx)
     return (np.array(tot[:]), rc) if not check else np.array(tot[:])
+
+
+def tvlbm_moments_static(ctx, fields=None, totals=None, flag=None):
+    """Asynchronous, allocation-free moments: fields (device [4][ny][nx]),
+    totals (device float64[4]) and flag (device int32[1]), each optional."""
+    _check(lib().tvlbm_moments_static(ctx, _ptr(fields), _ptr(totals), _ptr(flag)), ctx)
 
 
 def tvlbm_residual(ctx) -> float:
