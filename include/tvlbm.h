@@ -145,7 +145,14 @@ int tvlbm_moments_static(tvlbm_ctx *ctx, void *fields, double *totals, int32_t *
 int tvlbm_residual(tvlbm_ctx *ctx, double *r);
 
 /* Run until the residual over k_interval steps is below tol, or max_steps.
- * steps_done/r_final (host, may be NULL).  ENOTCONVERGED at the limit. */
+ * steps_done/r_final (host, may be NULL).  ENOTCONVERGED at the limit.
+ * FP32: at every residual check that does not stop the solve, the deviation
+ * mass of the state (tallied exactly, in 2^-32 fixed point) is compared
+ * with the solve's starting mass and the deficit is added back to the
+ * post-collision state as a uniform density increment at rest, delta w_l
+ * per cell: FP32 rounding of the collision moves the mass by up to ~1e-9
+ * of it per step where T != 1, which would otherwise add up over a long
+ * solve.  FP64 runs are left as stepped. */
 int tvlbm_solve(tvlbm_ctx *ctx, int64_t max_steps, double tol,
                 int32_t k_interval, int64_t *steps_done, double *r_final);
 
@@ -173,9 +180,9 @@ int tvlbm_load(tvlbm_ctx *ctx, const char *path);
  * bit.  0 = the default.  tvlbm_num_variants gives the count.  Some
  * variants advance two steps per launch (g^{k+2} from g^k in one sweep,
  * Sec. II's collide-and-stream map applied twice, each population read and
- * written once per two steps) on the grids that kernel covers (periodic
- * in y, uniform rows; FP32 with n_gh 3, 4 or 6, FP64 with n_gh 3 or 4);
- * elsewhere they run variant 0.
+ * written once per two steps) on the grids that kernel covers (uniform
+ * rows, periodic or with walls; FP32 with n_gh 3, 4 or 6, FP64 with n_gh 3
+ * or 4); elsewhere they run variant 0.
  * tvlbm_step(ctx, n) with such a variant makes floor((n-1)/2) two-step
  * launches and one or two single steps, so that the state after the call
  * is the same as with single steps. */
@@ -198,7 +205,7 @@ const char *tvlbm_last_error(const tvlbm_ctx *ctx);
 /* ------------------------------------------------------------------------
  * Batched steady solves: many independent channels (diffuse walls in y,
  * periodic in x, uniform rows) of different sizes, relaxation times and wall
- * states advanced together.  One persistent grid-stride kernel walks a
+ * states advanced together, by default two steps per launch.  One persistent grid-stride kernel walks a
  * device-resident work list of (instance, column strip, row segments); every
  * k_interval steps a per-instance residual (same definition as
  * tvlbm_residual) retires the instances below tol and the work list is
@@ -235,7 +242,8 @@ int tvlbm_batch_destroy(tvlbm_batch *b);
 /* f^0 = feq(fields) per instance; fields: device, packed as above. */
 int tvlbm_batch_set_fields(tvlbm_batch *b, const void *fields);
 /* Run every instance until its residual over k_interval (even, >= 2) steps
- * is below tol or it has taken max_steps.  steps_out (host, n_inst) gets the
+ * is below tol or it has taken max_steps.  FP32: as tvlbm_solve, the
+ * starting mass of every instance that goes on is put back at each check.  steps_out (host, n_inst) gets the
  * steps each instance took, r_out (host, n_inst, may be NULL) its last
  * residual.  Synchronises.  ENOTCONVERGED if any instance hit max_steps. */
 int tvlbm_batch_run(tvlbm_batch *b, int64_t max_steps, double tol,
@@ -258,9 +266,18 @@ typedef struct tvlbm_batch_tuning {
                        /* items of the tail shape below; 0: never             */
   int32_t tail_width;  /* 16, 32 or 64 columns                               */
   int32_t tail_rows;   /* rows per lane segment, 1..255                      */
+  int32_t two_step;    /* 1: two steps per launch (each population read and  */
+                       /* written once per two steps) when the lattice has    */
+                       /* that kernel (n_gh 3 or 4, or 6 in FP32) and         */
+                       /* k_interval >= 4; each k_interval chunk ends with    */
+                       /* 4 single steps (2 if k_interval = 2 mod 4); 0: one  */
+                       /* step per launch                                     */
+  int32_t two_rows;    /* two-step kernel: rows per segment, 1..255 (the tail */
+                       /* work list uses tail_rows)                           */
 } tvlbm_batch_tuning;
-/* Defaults: prefetch 1, tail_active 0, tail shape 64 x 1.  EINVAL on values
- * outside the ranges above.  Synchronises the batch's stream. */
+/* Defaults: prefetch 1, tail_active 0, tail shape 64 x 1, two_step 1,
+ * two_rows 8.  EINVAL on values outside the ranges above.  Synchronises the
+ * batch's stream. */
 int tvlbm_batch_set_tuning(tvlbm_batch *b, const tvlbm_batch_tuning *t);
 int tvlbm_batch_get_tuning(const tvlbm_batch *b, tvlbm_batch_tuning *t);
 

@@ -87,11 +87,46 @@ def _time_steps(b, steps, k_interval):
     return time.perf_counter() - t0
 
 
+TWO_ROWS = [4, 6, 8, 12, 16]
+TWO_TAIL_ROWS = [1, 2, 3, 4, 6]
+
+
+def _autotune_batch_two(instances, fresh, steps, k_interval, tail_fraction):
+    """Two steps per launch: rows per segment of the bulk work list, then of
+    the tail list (timed on the largest instances, with the tail list in use
+    from the start)."""
+    b = fresh(instances)
+    times = {}
+    _time_steps(b, steps, k_interval)  # warm-up (graph capture)
+    for r in TWO_ROWS:
+        b.set_tuning(two_step=1, two_rows=r)
+        times[r] = _time_steps(b, steps, k_interval)
+    rows = min(times, key=times.get)
+    b.close()
+    ny_max = max(d["ny"] for d in instances)
+    big = [d for d in instances if d["ny"] == ny_max][:16]
+    tb = fresh(big)
+    tt = {}
+    for r in TWO_TAIL_ROWS:
+        tb.set_tuning(two_step=1, two_rows=rows, tail_active=len(big), tail_rows=r)
+        _time_steps(tb, k_interval, k_interval)
+        tt[r] = _time_steps(tb, 4 * steps, k_interval)
+    tail_rows = min(tt, key=tt.get)
+    tb.close()
+    tail_active = max(1, int(len(instances) * tail_fraction))
+    return {"shapes": {}, "tuning": {"prefetch": 0, "tail_active": tail_active, "tail_width": 64,
+                                     "tail_rows": tail_rows, "two_step": 1, "two_rows": rows},
+            "two_rows_s": {str(k): round(v, 4) for k, v in times.items()},
+            "tail_rows_s": {str(k): round(v, 4) for k, v in tt.items()}}
+
+
 def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: str = "f32",
-                   tail_fraction: float = 0.25):
+                   tail_fraction: float = 0.25, n_gh: int = 4):
     """Launch tuning of the batched solve, timed on the instances themselves.
 
-    Bulk phase (every instance active): the (strip width, rows per segment)
+    Two steps per launch where the lattice has that kernel: rows per segment
+    of the bulk and of the tail work list.  Otherwise, bulk phase (every
+    instance active): the (strip width, rows per segment)
     of each size class (max N_x) by coordinate descent over the classes,
     then the prefetch switch.  Tail phase: the single shape used once at
     most tail_fraction of the instances remain, timed on the instances of
@@ -105,6 +140,8 @@ def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: st
         b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in insts])
         return b
 
+    if dtype == "f32" or n_gh in (3, 4):
+        return _autotune_batch_two(instances, fresh, steps, k_interval, tail_fraction)
     b = fresh(instances)
     max_nx = max(d["nx"] for d in instances)
     classes = list(SIZE_CLASSES)
@@ -152,7 +189,7 @@ def autotune_batch(instances, steps: int = 200, k_interval: int = 100, dtype: st
     tail_active = max(1, int(len(instances) * tail_fraction))
     return {"shapes": dict(choice),
             "tuning": {"prefetch": pf, "tail_active": tail_active, "tail_width": best[0],
-                       "tail_rows": best[1]}}
+                       "tail_rows": best[1], "two_step": 0, "two_rows": 8}}
 
 
 FV_SEG_ROWS = [4, 5, 6, 7, 8, 10, 12, 16]

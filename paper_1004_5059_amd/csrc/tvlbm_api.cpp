@@ -346,7 +346,7 @@ static bool pairs_ok(const tvlbm_ctx* c) {
 // Two steps per launch: periodic in y, uniform rows; FP32 D2Q9/D2Q16/D2Q36,
 // FP64 D2Q9/D2Q16 (FP64 D2Q36 would not fit the register file).
 static bool two_ok(const tvlbm_ctx* c) {
-  return kVariants[c->variant].two && !c->rows && c->d.y_bc == TVLBM_BC_PERIODIC &&
+  return kVariants[c->variant].two && !c->rows &&
          (c->hl.n == 3 || c->hl.n == 4 || (c->hl.n == 6 && !c->f64));
 }
 
@@ -472,14 +472,19 @@ static int run_march2(tvlbm_ctx* c, const void* src, void* dst) {
   std::memset(&A, 0, sizeof A);
   A.lat = lat_of<R>(c);
   A.inst = inst_of<R>(c);
+  const bool walls = c->d.y_bc == TVLBM_BC_DIFFUSE_WALLS;
   A.width = 64;
   A.rows = v.rows;
-  A.tiles_x = (int)ceil_div(c->d.nx, 62);
+  // strips of 62 output columns (one halo lane each side), 60 with walls
+  A.tiles_x = (int)ceil_div(c->d.nx, walls ? 60 : 62);
   A.n_tiles = (int)(A.tiles_x * ceil_div(ceil_div(c->d.ny, v.rows), 4));
   A.src = (const R*)src;
   A.dst = (R*)dst;
   const int nblocks = (int)(ceil_div(A.n_tiles, 8) * 8);
-  HIPCHK(c, launch_march2(c->hl.n, c->comp, A, nblocks, c->st));
+  if (walls)
+    HIPCHK(c, launch_march2w(c->hl.n, c->comp, A, nblocks, c->st));
+  else
+    HIPCHK(c, launch_march2(c->hl.n, c->comp, A, nblocks, c->st));
   return TVLBM_OK;
 }
 static int march2(tvlbm_ctx* c, const void* src, void* dst) {
@@ -1035,6 +1040,19 @@ struct tvlbm_batch {
   int tail_cap = 0;
   int prefetch = 1;
   int tail_active = 0, tail_width = 64, tail_rows = 1;
+  // Two steps per launch (k_march2_batch): its own bulk and tail work lists
+  // (rows per segment two_rows and tail_rows), used when two_step is set,
+  // the lattice has the kernel and K is a multiple of 4.
+  int two_step = 1, two_rows = 8;
+  Work* d_all2 = nullptr;
+  int32_t* d_item_start2 = nullptr;
+  Work* d_all2_tail = nullptr;
+  int32_t* d_item_start2_tail = nullptr;
+  int n_items2 = 0, n_items2_tail = 0, items2_cap = 0, tail2_cap = 0;
+  bool chunk_two = false;  // kind of the chunks the current graphs hold
+  // two-step chunks end with single steps, which walk this second live list
+  Work* d_work1 = nullptr;
+  int32_t* d_nwork1 = nullptr;
   hipGraphExec_t gexec_tail = nullptr;
   bool initialised = false;
   bool stepped = false;
@@ -1112,6 +1130,27 @@ void make_items(const tvlbm_batch* b, ShapeOf shape_of, std::vector<Work>& all,
   start[b->inst.size()] = (int32_t)all.size();
 }
 
+// Work items of the two-step kernel: strips of Wg - 4 output columns with
+// two halo lanes each side (Wg = 32 lanes for instances up to 28 columns
+// wide, else 64), 64 / Wg consecutive segments of `rows` rows per item.
+void make_items2(const tvlbm_batch* b, int rows, std::vector<Work>& all, std::vector<int32_t>& start) {
+  all.clear();
+  start.assign(b->inst.size() + 1, 0);
+  for (size_t k = 0; k < b->inst.size(); ++k) {
+    start[k] = (int32_t)all.size();
+    const tvlbm_inst& I = b->inst[k];
+    const int wg = I.nx <= 28 ? 32 : 64, G = 64 / wg;
+    const int nseg = (I.ny + rows - 1) / rows;
+    for (int x0 = 0; x0 < I.nx; x0 += wg - 4)
+      for (int sg = 0; sg < nseg; sg += G) all.push_back(Work{(int32_t)k, x0, sg, wg | (rows << 8)});
+  }
+  start[b->inst.size()] = (int32_t)all.size();
+}
+
+bool two_kernel(const tvlbm_batch* b) {
+  return b->hl.n == 3 || b->hl.n == 4 || (b->hl.n == 6 && !b->f64);
+}
+
 void drop_graphs(tvlbm_batch* b) {
   if (b->gexec) hipGraphExecDestroy(b->gexec);
   if (b->gexec_tail) hipGraphExecDestroy(b->gexec_tail);
@@ -1141,10 +1180,36 @@ int build_items(tvlbm_batch* b) {
     BHIP(b, hipMalloc(&b->d_all_tail, sizeof(Work) * b->n_items_tail));
     b->tail_cap = b->n_items_tail;
   }
-  // the live work list holds items of either list
+  std::vector<Work> all2, tail2;
+  std::vector<int32_t> start2, tail2_start;
+  make_items2(b, b->two_rows, all2, start2);
+  make_items2(b, b->tail_rows, tail2, tail2_start);
+  b->n_items2 = (int)all2.size();
+  b->n_items2_tail = (int)tail2.size();
+  if (b->n_items2 > b->items2_cap) {
+    hipFree(b->d_all2);
+    b->d_all2 = nullptr;
+    BHIP(b, hipMalloc(&b->d_all2, sizeof(Work) * b->n_items2));
+    b->items2_cap = b->n_items2;
+  }
+  if (b->n_items2_tail > b->tail2_cap) {
+    hipFree(b->d_all2_tail);
+    b->d_all2_tail = nullptr;
+    BHIP(b, hipMalloc(&b->d_all2_tail, sizeof(Work) * b->n_items2_tail));
+    b->tail2_cap = b->n_items2_tail;
+  }
+  BHIP(b, hipMemcpy(b->d_all2, all2.data(), sizeof(Work) * all2.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_item_start2, start2.data(), sizeof(int32_t) * start2.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_all2_tail, tail2.data(), sizeof(Work) * tail2.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_item_start2_tail, tail2_start.data(), sizeof(int32_t) * tail2_start.size(),
+                    hipMemcpyHostToDevice));
+  // the live work lists: items of any one list / of a one-step list
   hipFree(b->d_work);
-  b->d_work = nullptr;
-  BHIP(b, hipMalloc(&b->d_work, sizeof(Work) * std::max(b->n_items, b->n_items_tail)));
+  hipFree(b->d_work1);
+  b->d_work = b->d_work1 = nullptr;
+  const int cap = std::max(std::max(b->n_items, b->n_items_tail), std::max(b->n_items2, b->n_items2_tail));
+  BHIP(b, hipMalloc(&b->d_work, sizeof(Work) * cap));
+  BHIP(b, hipMalloc(&b->d_work1, sizeof(Work) * std::max(b->n_items, b->n_items_tail)));
   BHIP(b, hipMemcpy(b->d_all, all.data(), sizeof(Work) * all.size(), hipMemcpyHostToDevice));
   BHIP(b, hipMemcpy(b->d_item_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice));
   if (b->n_items_tail > 0) {
@@ -1191,9 +1256,33 @@ int bmarch(tvlbm_batch* b, int mode, int aux, const void* src, void* dst, const 
 // Rebuild the live work list from the active instances' items of the bulk
 // or the tail list.
 int compact(tvlbm_batch* b, bool tail) {
-  BHIP(b, launch_batch_compact(b->d_active, tail ? b->d_item_start_tail : b->d_item_start,
-                               tail ? b->d_all_tail : b->d_all, b->d_work, b->d_nwork,
-                               b->d_remaining, (int)b->inst.size(), b->st));
+  const int32_t* start1 = tail ? b->d_item_start_tail : b->d_item_start;
+  const Work* all1 = tail ? b->d_all_tail : b->d_all;
+  if (b->chunk_two) {
+    BHIP(b, launch_batch_compact(b->d_active, tail ? b->d_item_start2_tail : b->d_item_start2,
+                                 tail ? b->d_all2_tail : b->d_all2, b->d_work, b->d_nwork,
+                                 b->d_remaining, (int)b->inst.size(), b->st));
+    BHIP(b, launch_batch_compact(b->d_active, start1, all1, b->d_work1, b->d_nwork1, b->d_remaining,
+                                 (int)b->inst.size(), b->st));
+  } else {
+    BHIP(b, launch_batch_compact(b->d_active, start1, all1, b->d_work, b->d_nwork, b->d_remaining,
+                                 (int)b->inst.size(), b->st));
+  }
+  return TVLBM_OK;
+}
+
+// Two-step launch over the live work list.
+template <typename R>
+int batch_march2(tvlbm_batch* b, const void* src, void* dst, int nblocks) {
+  MarchArgs<R> A;
+  std::memset(&A, 0, sizeof A);
+  A.lat = std::is_same<R, float>::value ? *(Lat<R>*)(void*)&b->latf : *(Lat<R>*)(void*)&b->latd;
+  A.insts = (const Inst<R>*)b->d_insts;
+  A.work = b->d_work;
+  A.n_work = b->d_nwork;
+  A.src = (const R*)src;
+  A.dst = (R*)dst;
+  BHIP(b, launch_march2_batch(b->hl.n, b->comp, A, nblocks, b->st));
   return TVLBM_OK;
 }
 
@@ -1221,14 +1310,36 @@ int batch_resid(tvlbm_batch* b, int K, double tol, int64_t max_steps) {
 // and the compaction of the work list.  At chunk boundaries every instance's
 // post-collision state is in buf[0] (K is even).
 int enqueue_chunk(tvlbm_batch* b, int K, double tol, int64_t max_steps, bool tail) {
-  const int nblocks = batch_blocks(tail ? b->n_items_tail : b->n_items);
   const int n = (int)b->inst.size();
   BHIP(b, launch_fill_i32((int32_t*)b->d_mass, 2 * n, 0, b->st));
-  for (int s = 0; s < K; ++s) {
-    const int mode = (s == K - 1) ? MODE_CHECK : MODE_STEP;
-    int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work, nblocks,
+  if (b->chunk_two) {
+    // n2 two-step launches, then n1 single steps (the last one the check):
+    // the other buffer ends with g^{K-1}, and n2 + n1 is even, so the state
+    // returns to buf[0]
+    const int n1 = (K % 4 == 0) ? 4 : 2, n2 = (K - n1) / 2;
+    const int nb2 = batch_blocks(tail ? b->n_items2_tail : b->n_items2);
+    const int nb1 = batch_blocks(tail ? b->n_items_tail : b->n_items);
+    for (int s = 0; s < n2 + n1; ++s) {
+      const void* src = b->buf[s & 1];
+      void* dst = b->buf[(s & 1) ^ 1];
+      int rc;
+      if (s < n2) {
+        rc = b->f64 ? batch_march2<double>(b, src, dst, nb2) : batch_march2<float>(b, src, dst, nb2);
+      } else {
+        const int mode = (s == n2 + n1 - 1) ? MODE_CHECK : MODE_STEP;
+        rc = bmarch(b, mode, 0, src, dst, b->d_nwork1, b->d_work1, nb1,
                     mode == MODE_CHECK ? b->d_mass : nullptr);
-    if (rc) return rc;
+      }
+      if (rc) return rc;
+    }
+  } else {
+    const int nblocks = batch_blocks(tail ? b->n_items_tail : b->n_items);
+    for (int s = 0; s < K; ++s) {
+      const int mode = (s == K - 1) ? MODE_CHECK : MODE_STEP;
+      int rc = bmarch(b, mode, 0, b->buf[s & 1], b->buf[(s & 1) ^ 1], b->d_nwork, b->d_work, nblocks,
+                      mode == MODE_CHECK ? b->d_mass : nullptr);
+      if (rc) return rc;
+    }
   }
   int rc = b->f64 ? batch_resid<double>(b, K, tol, max_steps) : batch_resid<float>(b, K, tol, max_steps);
   if (rc) return rc;
@@ -1281,7 +1392,8 @@ int tvlbm_batch_destroy(tvlbm_batch* b) {
   drop_graphs(b);
   hipFree(b->d_insts); hipFree(b->d_all); hipFree(b->d_work); hipFree(b->d_item_start);
   hipFree(b->d_all_tail); hipFree(b->d_item_start_tail);
-  hipFree(b->d_rpart); hipFree(b->d_nwork); hipFree(b->d_ntotal); hipFree(b->d_remaining);
+  hipFree(b->d_all2); hipFree(b->d_item_start2); hipFree(b->d_all2_tail); hipFree(b->d_item_start2_tail);
+  hipFree(b->d_rpart); hipFree(b->d_nwork); hipFree(b->d_nwork1); hipFree(b->d_work1); hipFree(b->d_ntotal); hipFree(b->d_remaining);
   hipFree(b->d_active); hipFree(b->d_have_prev); hipFree(b->d_steps); hipFree(b->d_resid);
   hipFree(b->d_flag); hipFree(b->d_fields); hipFree(b->d_prev);
   hipFree(b->d_mass0); hipFree(b->d_mass); hipFree(b->d_area);
@@ -1335,8 +1447,11 @@ int tvlbm_batch_init(const tvlbm_batch_desc* d, tvlbm_batch** out) {
   bool ok = hipMalloc(&b->d_insts, isz * n) == hipSuccess &&
             hipMalloc(&b->d_item_start, sizeof(int32_t) * (n + 1)) == hipSuccess &&
             hipMalloc(&b->d_item_start_tail, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            hipMalloc(&b->d_item_start2, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            hipMalloc(&b->d_item_start2_tail, sizeof(int32_t) * (n + 1)) == hipSuccess &&
             hipMalloc(&b->d_rpart, sizeof(double) * 2 * RESID_SLICES * n) == hipSuccess &&
             hipMalloc(&b->d_nwork, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_nwork1, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_ntotal, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_remaining, sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_active, sizeof(int32_t) * n) == hipSuccess &&
@@ -1385,13 +1500,16 @@ int tvlbm_batch_set_shape(tvlbm_batch* b, int32_t max_nx, int32_t width, int32_t
 int tvlbm_batch_set_tuning(tvlbm_batch* b, const tvlbm_batch_tuning* t) {
   if (!b || !t || (t->prefetch != 0 && t->prefetch != 1) || t->tail_active < 0 ||
       !(t->tail_width == 16 || t->tail_width == 32 || t->tail_width == 64) || t->tail_rows < 1 ||
-      t->tail_rows > 255)
+      t->tail_rows > 255 || (t->two_step != 0 && t->two_step != 1) || t->two_rows < 1 ||
+      t->two_rows > 255)
     return bfail(b, TVLBM_EINVAL, "tuning");
   BHIP(b, hipStreamSynchronize(b->st));
   b->prefetch = t->prefetch;
   b->tail_active = t->tail_active;
   b->tail_width = t->tail_width;
   b->tail_rows = t->tail_rows;
+  b->two_step = t->two_step;
+  b->two_rows = t->two_rows;
   return build_items(b);
 }
 
@@ -1401,6 +1519,8 @@ int tvlbm_batch_get_tuning(const tvlbm_batch* b, tvlbm_batch_tuning* t) {
   t->tail_active = b->tail_active;
   t->tail_width = b->tail_width;
   t->tail_rows = b->tail_rows;
+  t->two_step = b->two_step;
+  t->two_rows = b->two_rows;
   return TVLBM_OK;
 }
 
@@ -1460,8 +1580,10 @@ int tvlbm_batch_run(tvlbm_batch* b, int64_t max_steps, double tol, int32_t K, in
   }
   BHIP(b, hipMemcpyAsync(b->d_have_prev, ones.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->st));
   BHIP(b, hipMemcpyAsync(b->d_steps, zeros64.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, b->st));
-  if (b->g_K != K || b->g_tol != tol || b->g_max != max_steps) drop_graphs(b);
+  const bool two = b->two_step && two_kernel(b) && K >= 4;
+  if (b->g_K != K || b->g_tol != tol || b->g_max != max_steps || b->chunk_two != two) drop_graphs(b);
   b->g_K = K; b->g_tol = tol; b->g_max = max_steps;
+  b->chunk_two = two;
   auto want_tail = [b](int remaining) { return b->tail_active > 0 && remaining <= b->tail_active; };
   bool tail = want_tail(n);
   int rc = compact(b, tail);

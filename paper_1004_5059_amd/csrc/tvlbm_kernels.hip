@@ -480,14 +480,15 @@ __device__ __forceinline__ double lane_from(double v) {
 
 // moments, Hermite equilibrium and BGK of one cell, result in registers
 template <typename R, int N, int ORD, bool COMP>
-__device__ __forceinline__ void collide_regs(const Lat<R>& L, const Inst<R>& P,
-                                             const R (&d)[N * N], R (&g)[N * N]) {
+__device__ __forceinline__ Fields<R> collide_regs(const Lat<R>& L, const Inst<R>& P,
+                                                  const R (&d)[N * N], R (&g)[N * N]) {
   R drho, jx, jy, ed;
   cell_moments<R, N, COMP>(L, d, drho, jx, jy, ed);
   const Fields<R> F = fields_from(drho, jx, jy, ed);
 #pragma unroll
   for (int l = 0; l < N * N; ++l) g[l] = d[l];
   bgk_cell<R, N, ORD>(L, P, F, g);
+  return F;
 }
 
 __device__ __forceinline__ int wrap_row(int j, int ny) {
@@ -639,6 +640,294 @@ __global__ __launch_bounds__(256) void k_march2(const MarchArgs<R> A) {
     march2_dir<R, N, ORD, COMP, -1>(A, ic, im, ip, active, j0, j1);
   else
     march2_dir<R, N, ORD, COMP, +1>(A, ic, im, ip, active, j0, j1);
+}
+
+// ------------------------------------------- two steps per sweep, walls --
+// Two-step march on grids with diffuse walls in y (uniform rows), for the
+// walled single grid and the batched channels.  As k_march2, but:
+//  * the first step on a wall row pulls the populations coming from beyond
+//    the wall from that wall's ghost of g^k (the re-emitted incident mass,
+//    eq.(IMPOSITION)), exactly as the one-step march does;
+//  * rows beyond a wall are not computed.  When an output row is a wall row
+//    whose upstream row lies beyond the wall, the second step takes the
+//    x-pulled ghost of g^{k+1} instead: the incident mass of the wall row's
+//    g^{k+1} per column (x-pulled values of this lane) and, for the ghost's
+//    own x-pull, of the neighbouring columns (DPP lane shifts).  The ghost's
+//    x-reach is two columns (incident x-pull, then emitted x-pull), so a
+//    strip carries two halo lanes on each side;
+// Every output cell sees the operations of two one-step launches in the
+// same order, so the result is bitwise that of the one-step march.
+//
+// Per lane: segment [j0, j1) (live = the segment exists), its column
+// ic (im, ip: periodic neighbours), active = stores.  nt = uniform trip count
+// (rows per segment + 2).  Lanes of one segment share every branch below.
+template <typename R, int N, int ORD, bool COMP, int DIR>
+__device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Inst<R>& P, int ic,
+                                                int im, int ip, bool active, bool live, int j0,
+                                                int j1, int nt) {
+  constexpr int Q = N * N;
+  const Lat<R>& L = A.lat;
+  const int ny = P.ny, nx = P.nx;
+  const int64_t plane = P.plane;
+  const uint32_t ld = (uint32_t)P.ld;
+  const uint32_t bytes = (uint32_t)(Q * plane * (int64_t)sizeof(R));
+  const rsrc_t s = make_rsrc(A.src + P.off, bytes);
+  const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
+  const int nout = j1 - j0;
+  const int jf = DIR > 0 ? j0 : j1 - 1;  // first output row
+  const int jl = DIR > 0 ? j1 - 1 : j0;  // last output row
+  // an output row at either end whose upstream row lies beyond a wall
+  const bool gh_first = DIR > 0 ? jf == 0 : jf == ny - 1;
+  const bool gh_last = DIR > 0 ? jl == ny - 1 : jl == 0;
+  const int t_first = gh_first ? 1 : 0;         // first-step rows computed: t_first..t_last
+  const int t_last = gh_last ? nout : nout + 1;
+  const int rf = jf + (t_first - 1) * DIR, rl = jf + (t_last - 1) * DIR;
+  // the first / last computed row is a wall row pulling from beyond it
+  const bool wall_first = DIR > 0 ? rf == 0 : rf == ny - 1;
+  const bool wall_last = DIR > 0 ? rl == ny - 1 : rl == 0;
+
+  R hp[Q];
+  if (live) {
+    R m_c = R(0), m_m = R(0), m_p = R(0);
+    if (wall_first) {
+      const uint32_t rw = (uint32_t)rf * ld;
+      m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, -DIR);
+      m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, -DIR);
+      m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, -DIR);
+    }
+    const RowOff ob = row_off((uint32_t)(rf - DIR) * ld, ic, im, ip);  // unused when wall_first
+    const RowOff of = row_off((uint32_t)rf * ld, ic, im, ip);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        if (sg == DIR)
+          hp[l] = wall_first ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p)
+                             : xpull<R, N>(L, s, (uint32_t)(l * plane), a, ob);
+        else if (sg == -DIR)
+          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, of);
+        else
+          hp[l] = R(0);
+      }
+    }
+  }
+
+  R y1[Q], y2[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) y1[l] = y2[l] = R(0);
+  for (int t = 0; t < nt; ++t) {
+    const int r = jf + (t - 1) * DIR;
+    R x[Q];
+    if (live && t >= t_first && t <= t_last) {
+      // first step on row r
+      const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
+      const bool ghost_next = wall_last && t == t_last;  // row r + DIR beyond a wall
+      R m_c = R(0), m_m = R(0), m_p = R(0);
+      if (ghost_next) {
+        const uint32_t rw = (uint32_t)r * ld;
+        m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, DIR);
+        m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, DIR);
+        m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, DIR);
+      }
+      const RowOff on = row_off((uint32_t)(r + DIR) * ld, ic, im, ip);
+      R d[Q];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const int sg = node_sign<N>(b);
+          const uint32_t pl = (uint32_t)(l * plane);
+          if (sg == DIR) {  // lead
+            const R hn = xpull<R, N>(L, s, pl, a, oj);
+            d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
+            hp[l] = hn;
+          } else if (sg == -DIR) {  // trail
+            const R hn = ghost_next ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p)
+                                    : xpull<R, N>(L, s, pl, a, on);
+            d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
+            hp[l] = hn;
+          } else {
+            d[l] = xpull<R, N>(L, s, pl, a, oj);
+          }
+        }
+      }
+      R g[Q];
+      collide_regs<R, N, ORD, COMP>(L, P, d, g);
+      // x part of the second remap: upstream column from the neighbouring
+      // lane (lanes of this segment all take this branch; a neighbour in
+      // another segment is a halo lane's, whose results are not stored)
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const int sa = node_sign<N>(a);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          if (sa > 0)
+            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
+          else if (sa < 0)
+            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
+          else
+            x[l] = g[l];
+        }
+      }
+    } else {
+      // no row here (beyond a wall, or past the segment): placeholder values
+      // that no output uses (the trail ones are replaced by a ghost below)
+#pragma unroll
+      for (int l = 0; l < Q; ++l) x[l] = y1[l];
+    }
+    if (live && gh_first && t == 1) {
+      // ghost of g^{k+1} behind the first output row (a wall row): mass its
+      // populations carry through that wall, re-emitted into the lead ones
+      R m = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        if (node_sign<N>(b) != -DIR) continue;
+        R acc = R(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc += x[a * N + b];
+        m = fmaR(L.p[b], acc, m);
+      }
+      const R m_m = lane_from<DPP_PREV>(m), m_p = lane_from<DPP_NEXT>(m);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == DIR) y1[a * N + b] = ghost_of<R, N>(L, P, a, b, m, m_m, m_p);
+      }
+    }
+    if (live && gh_last && t == nout + 1) {
+      // ghost of g^{k+1} beyond the last output row (a wall row), from that
+      // row's x-pulled g^{k+1} (in y1), re-emitted into the trail populations
+      R m = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        if (node_sign<N>(b) != DIR) continue;
+        R acc = R(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc += y1[a * N + b];
+        m = fmaR(L.p[b], acc, m);
+      }
+      const R m_m = lane_from<DPP_PREV>(m), m_p = lane_from<DPP_NEXT>(m);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == -DIR) x[a * N + b] = ghost_of<R, N>(L, P, a, b, m, m_m, m_p);
+      }
+    }
+    if (live && t >= 2 && t <= nout + 1) {  // second step on output row r - DIR
+      const int mrow = r - DIR;
+      R e[Q];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const int sg = node_sign<N>(b);
+          if (sg == DIR)
+            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * y2[l]);
+          else if (sg == -DIR)
+            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * x[l]);
+          else
+            e[l] = y1[l];
+        }
+      }
+      R g2[Q];
+      collide_regs<R, N, ORD, COMP>(L, P, e, g2);
+      if (active) {
+        const uint32_t om = (uint32_t)mrow * ld + (uint32_t)ic;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) bst(dst, om, (uint32_t)(l * plane), g2[l]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        if (node_sign<N>(b) == DIR) y2[l] = y1[l];
+        y1[l] = x[l];
+      }
+    }
+  }
+}
+
+
+// Walled grid, one instance: workgroup = 4 wavefronts = 4 consecutive row
+// segments of a strip of 60 output columns (two halo lanes on each side).
+constexpr int STRIP2W = 60;
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_march2w(const MarchArgs<R> A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;  // multiple of 8
+  const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (t >= A.n_tiles) return;
+  const Inst<R>& P = A.inst;
+  const int nx = P.nx, ny = P.ny;
+  const int tx = t % A.tiles_x, ty = t / A.tiles_x;
+  const int group = ty * 4 + wave;
+  const int j0 = group * A.rows;
+  if (j0 >= ny) return;  // wave-uniform
+  const int j1 = min(j0 + A.rows, ny);
+  const int col = tx * STRIP2W - 2 + lane;
+  const bool active = lane >= 2 && lane < 64 - 2 && col < nx;
+  int ic = col % nx;
+  ic = ic < 0 ? ic + nx : ic;
+  const int im = ic == 0 ? nx - 1 : ic - 1;
+  const int ip = ic == nx - 1 ? 0 : ic + 1;
+  if (group & 1)
+    march2_wall_seg<R, N, ORD, COMP, -1>(A, P, ic, im, ip, active, true, j0, j1, j1 - j0 + 2);
+  else
+    march2_wall_seg<R, N, ORD, COMP, +1>(A, P, ic, im, ip, active, true, j0, j1, j1 - j0 + 2);
+}
+
+// Batched walled channels, two steps per launch: persistent grid-stride
+// over the live work list as k_march_batch.  An item is one strip of an
+// instance (Wg - 4 output columns, two halo lanes each side, Wg = 32 or 64
+// lanes) and 64 / Wg consecutive row segments, one per lane group; the
+// groups of a wavefront march in the same direction.  A chunk of steps ends
+// with single-step launches (the library's state semantics: the other
+// buffer holds g^{k-1}), which also do the check mode.
+template <typename R, int N, int ORD, bool COMP>
+__global__ __launch_bounds__(256) void k_march2_batch(const MarchArgs<R> A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_work = *A.n_work;
+  int lo = 0, hi = n_work, first = blockIdx.x * 4 + wave, stride = gridDim.x * 4;
+  if ((gridDim.x & 7) == 0) {  // one contiguous range of the list per XCD
+    const int x = blockIdx.x & 7;
+    lo = (int)((int64_t)n_work * x / 8);
+    hi = (int)((int64_t)n_work * (x + 1) / 8);
+    first = lo + (int)(blockIdx.x >> 3) * 4 + wave;
+    stride = (int)(gridDim.x >> 3) * 4;
+  }
+  for (int w = first; w < hi; w += stride) {
+    const Work it = A.work[w];
+    const Inst<R>& P = A.insts[it.inst];
+    const int Wg = it.shape & 0xff, rows = (it.shape >> 8) & 0xff;
+    const int G = 64 / Wg;
+    const int gl = lane & (Wg - 1), g = lane / Wg;
+    const int seg = it.seg0 + g;
+    const int j0 = seg * rows;
+    const bool live = j0 < P.ny;
+    const int j1 = min(j0 + rows, P.ny);
+    const int nx = P.nx;
+    const int col = it.x0 - 2 + gl;
+    const bool active = live && gl >= 2 && gl < Wg - 2 && col < nx;
+    int ic = col % nx;
+    ic = ic < 0 ? ic + nx : ic;
+    const int im = ic == 0 ? nx - 1 : ic - 1;
+    const int ip = ic == nx - 1 ? 0 : ic + 1;
+    if ((it.seg0 / G) & 1)
+      march2_wall_seg<R, N, ORD, COMP, -1>(A, P, ic, im, ip, active, live, j0, j1, rows + 2);
+    else
+      march2_wall_seg<R, N, ORD, COMP, +1>(A, P, ic, im, ip, active, live, j0, j1, rows + 2);
+  }
 }
 
 // ------------------------------------------------------- non-uniform rows --
@@ -1121,6 +1410,54 @@ hipError_t launch_march2(int n, bool comp, const MarchArgs<float>& A, int nblock
 hipError_t launch_march2(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st) {
   (void)comp;  // FP64 sums need no compensation
   return march2_lat<double, false>(n, A, nblocks, st);
+}
+
+template <typename R, bool COMP>
+static hipError_t march2w_lat(int n, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (n) {
+    case 3: hipLaunchKernelGGL((k_march2w<R, 3, 2, COMP>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_march2w<R, 4, 3, COMP>), g, b, 0, st, A); break;
+    case 6:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_march2w<R, 6, 4, COMP>), g, b, 0, st, A);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_march2w(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
+  return comp ? march2w_lat<float, true>(n, A, nblocks, st) : march2w_lat<float, false>(n, A, nblocks, st);
+}
+hipError_t launch_march2w(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st) {
+  (void)comp;
+  return march2w_lat<double, false>(n, A, nblocks, st);
+}
+
+template <typename R, bool COMP>
+static hipError_t march2_batch_lat(int n, const MarchArgs<R>& A, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(256);
+  switch (n) {
+    case 3: hipLaunchKernelGGL((k_march2_batch<R, 3, 2, COMP>), g, b, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_march2_batch<R, 4, 3, COMP>), g, b, 0, st, A); break;
+    case 6:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_march2_batch<R, 6, 4, COMP>), g, b, 0, st, A);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_march2_batch(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st) {
+  return comp ? march2_batch_lat<float, true>(n, A, nblocks, st) : march2_batch_lat<float, false>(n, A, nblocks, st);
+}
+hipError_t launch_march2_batch(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st) {
+  (void)comp;
+  return march2_batch_lat<double, false>(n, A, nblocks, st);
 }
 
 template <typename R, bool COMP>

@@ -62,6 +62,14 @@ hipError_t launch_march2(int n, bool comp, const MarchArgs<float>& A, int nblock
 hipError_t launch_march2(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st);
 hipError_t launch_march(int n, bool comp, int mode, const MarchArgs<double>& A, int nblocks,
                         hipStream_t st);
+// Two steps per launch on a grid with diffuse walls in y (uniform rows): as
+// launch_march2 with strips of 60 output columns (A.tiles_x = ceil(nx/60)).
+hipError_t launch_march2w(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st);
+hipError_t launch_march2w(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st);
+// Batched walled channels, two steps per launch; work items of the
+// two-step shape (lane-group width | rows << 8).
+hipError_t launch_march2_batch(int n, bool comp, const MarchArgs<float>& A, int nblocks, hipStream_t st);
+hipError_t launch_march2_batch(int n, bool comp, const MarchArgs<double>& A, int nblocks, hipStream_t st);
 hipError_t launch_init(int n, bool comp, const InitArgs<float>& A, hipStream_t st);
 hipError_t launch_init(int n, bool comp, const InitArgs<double>& A, hipStream_t st);
 hipError_t launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t st);

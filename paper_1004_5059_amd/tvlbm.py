@@ -90,7 +90,8 @@ class tvlbm_batch_desc(ctypes.Structure):
 
 class tvlbm_batch_tuning(ctypes.Structure):
     _fields_ = [("prefetch", ctypes.c_int32), ("tail_active", ctypes.c_int32),
-                ("tail_width", ctypes.c_int32), ("tail_rows", ctypes.c_int32)]
+                ("tail_width", ctypes.c_int32), ("tail_rows", ctypes.c_int32),
+                ("two_step", ctypes.c_int32), ("two_rows", ctypes.c_int32)]
 
 
 class tvlbm_fv_desc(ctypes.Structure):
@@ -487,8 +488,10 @@ def tvlbm_batch_set_shape(h, max_nx: int, width: int, rows: int):
     _check(lib().tvlbm_batch_set_shape(h, int(max_nx), int(width), int(rows)))
 
 
-def tvlbm_batch_set_tuning(h, prefetch: int, tail_active: int, tail_width: int, tail_rows: int):
-    t = tvlbm_batch_tuning(int(prefetch), int(tail_active), int(tail_width), int(tail_rows))
+def tvlbm_batch_set_tuning(h, prefetch: int, tail_active: int, tail_width: int, tail_rows: int,
+                           two_step: int = 1, two_rows: int = 8):
+    t = tvlbm_batch_tuning(int(prefetch), int(tail_active), int(tail_width), int(tail_rows),
+                           int(two_step), int(two_rows))
     _check(lib().tvlbm_batch_set_tuning(h, ctypes.byref(t)))
 
 
@@ -496,7 +499,7 @@ def tvlbm_batch_get_tuning(h):
     t = tvlbm_batch_tuning()
     _check(lib().tvlbm_batch_get_tuning(h, ctypes.byref(t)))
     return {"prefetch": t.prefetch, "tail_active": t.tail_active, "tail_width": t.tail_width,
-            "tail_rows": t.tail_rows}
+            "tail_rows": t.tail_rows, "two_step": t.two_step, "two_rows": t.two_rows}
 
 
 class BatchSolver:
@@ -583,8 +586,9 @@ class BatchSolver:
         tvlbm_batch_set_shape(self.h, max_nx, width, rows)
 
     def set_tuning(self, prefetch: int = 1, tail_active: int = 0, tail_width: int = 64,
-                   tail_rows: int = 1):
-        tvlbm_batch_set_tuning(self.h, prefetch, tail_active, tail_width, tail_rows)
+                   tail_rows: int = 1, two_step: int = 1, two_rows: int = 8):
+        tvlbm_batch_set_tuning(self.h, prefetch, tail_active, tail_width, tail_rows, two_step,
+                               two_rows)
 
     def tuning(self):
         return tvlbm_batch_get_tuning(self.h)

@@ -99,13 +99,20 @@ def test_batch_retires_converged_instances_like_single_solves():
 
 @pytest.mark.parametrize("tuning", [dict(prefetch=0), dict(prefetch=1, tail_active=1, tail_rows=1),
                                     dict(prefetch=0, tail_active=2, tail_width=32, tail_rows=2),
-                                    dict(prefetch=0, tail_active=3, tail_width=16, tail_rows=5)])
+                                    dict(prefetch=0, tail_active=3, tail_width=16, tail_rows=5),
+                                    dict(two_step=0),
+                                    dict(two_step=0, tail_active=2, tail_width=32, tail_rows=2),
+                                    dict(two_step=1, two_rows=3),
+                                    dict(two_step=1, two_rows=16, tail_active=1, tail_rows=1),
+                                    dict(two_step=1, two_rows=5, tail_active=3, tail_rows=7)])
 def test_batch_tuning_does_not_change_results(tuning):
-    """Prefetch on/off and the switch to the tail work list (taken when the
-    first instance retires, or from the start when tail_active >= n) keep the
-    steps and the fields bitwise."""
+    """Prefetch on/off, one or two steps per launch (rows per segment), and
+    the switch to the tail work list (taken when the first instance retires,
+    or from the start when tail_active >= n) keep the steps and the fields
+    bitwise."""
     inst = [dict(nx=16, ny=32, tau=0.9, u_top=0.04, T_top=1.1),
-            dict(nx=40, ny=48, tau=0.6, u_top=0.02, T_top=1.05)]
+            dict(nx=40, ny=48, tau=0.6, u_top=0.02, T_top=1.05),
+            dict(nx=70, ny=36, tau=0.75, u_top=0.05, T_top=1.15)]
     res = []
     for t in (None, tuning):
         b = BatchSolver(inst, dtype="f32")
@@ -126,7 +133,7 @@ def test_batch_tuning_does_not_change_results(tuning):
 def test_batch_tuning_rejects_bad_values():
     b = BatchSolver(INST[:1], dtype="f32")
     for bad in [dict(prefetch=2), dict(tail_active=-1), dict(tail_width=48), dict(tail_rows=0),
-                dict(tail_rows=256)]:
+                dict(tail_rows=256), dict(two_step=2), dict(two_rows=0), dict(two_rows=256)]:
         with pytest.raises(Exception):
             b.set_tuning(**bad)
     b.close()
@@ -161,3 +168,19 @@ def test_fp32_steady_solves_keep_their_mass():
         assert abs(tot[0] - m0) / m0 <= 1e-6
         assert np.array_equal(to_np(fld), f)
         s.close()
+
+
+def test_batch_two_step_k_not_multiple_of_four():
+    """K = 50 (chunks of 24 two-step launches and two single steps): the same
+    result as one step per launch."""
+    inst = INST[:3]
+    res = []
+    for t in (dict(two_step=0), dict(two_step=1)):
+        b = BatchSolver(inst, dtype="f32")
+        b.set_tuning(**t)
+        b.set_fields([inputs.uniform_fields(d["nx"], d["ny"]) for d in inst])
+        b.run(max_steps=150, tol=0.0, k_interval=50)
+        res.append(b.fields())
+        b.close()
+    for a, c in zip(*res):
+        assert np.array_equal(a, c)

@@ -2,9 +2,11 @@
 the one-step march: bitwise equal populations, fields and totals after odd
 and even step counts, on widths around the 62-column strips and on heights
 down to two rows, D2Q9, D2Q16 and D2Q36, compensated and plain sums; the
-grids the variant does not apply to (walls, FP64 D2Q36) run the one-step
-march; FP64 D2Q9/D2Q16 bitwise as well;
-and the oracle on a ragged grid."""
+grids the variant does not apply to (non-uniform rows, FP64 D2Q36) run the
+one-step march; FP64 D2Q9/D2Q16 bitwise as well; and the oracle on a ragged
+grid.  With diffuse walls (strips of 60 columns, the walls' ghosts of the
+intermediate step formed in the sweep) the same bitwise equality on widths
+around the strip and heights down to two rows, and the oracle.""" 
 import numpy as np
 import pytest
 
@@ -39,7 +41,11 @@ def test_variant_table_has_the_two_step_entries():
     assert s.steps_per_launch() == 1
     s.close()
     s = _solver(64, 16, 4, TWO[0], walls=True)
-    assert s.steps_per_launch() == 1
+    assert s.steps_per_launch() == 2
+    s.close()
+    s = Solver(64, 16, n_gh=4, dtype="f32", tau=0.7, walls=True, dy=np.r_[np.full(4, 0.5), np.ones(14)][:16])
+    s.set_variant(TWO[0])
+    assert s.steps_per_launch() == 1  # non-uniform rows
     s.close()
     s = _solver(64, 16, 4, TWO[0], dtype="f64")
     assert s.steps_per_launch() == 2
@@ -88,13 +94,20 @@ def test_two_step_plain_and_compensated_sums(compensated):
     a.close(), b.close()
 
 
-@pytest.mark.parametrize("kw", [dict(walls=True), dict(n=6, walls=True), dict(n=6, dtype="f64"),
-                                dict(dtype="f64", walls=True)])
+@pytest.mark.parametrize("kw", [dict(n=6, dtype="f64"), dict(n=6, dtype="f64", walls=True),
+                                dict(refined=True), dict(refined=True, walls=True)])
 def test_grids_outside_the_two_step_kernel_run_the_one_step_march(kw):
     n = kw.pop("n", 4)
     nx, ny = 70, 29
     fields, noise = c0_inputs(nx, ny, q=n * n, seed=9)
-    a, b = _solver(nx, ny, n, 0, **kw), _solver(nx, ny, n, 22, **kw)
+    if kw.pop("refined", False):
+        dy = np.r_[np.full(6, 0.5), np.ones(ny - 6)]
+        a = Solver(nx, ny, n_gh=n, tau=0.7, dy=dy, **kw)
+        b = Solver(nx, ny, n_gh=n, tau=0.7, dy=dy, **kw)
+        b.set_variant(22)
+    else:
+        a, b = _solver(nx, ny, n, 0, **kw), _solver(nx, ny, n, 22, **kw)
+    assert b.steps_per_launch() == 1
     for s in (a, b):
         s.set_fields(*fields, noise)
         s.step(9)
@@ -216,4 +229,72 @@ def test_c0_shear_wave_two_step_fp64(variant):
     s.step(200)
     fr = g.run(g.set_fields(*fields, noise), 200)
     assert rel_inf(s.populations().cpu().numpy(), fr) <= 1e-12
+    s.close()
+
+
+WALLS = dict(walls=True, wall_lo=(-0.01, 0.97), wall_hi=(0.04, 1.12))
+
+
+def _wsolver(nx, ny, n, variant, dtype="f32", tau=0.7):
+    s = Solver(nx, ny, n_gh=n, dtype=dtype, tau=tau, **WALLS)
+    s.set_variant(variant)
+    return s
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (5, 3), (59, 9), (60, 17), (61, 2), (121, 33),
+                                   (130, 40), (190, 5)])
+def test_walled_two_step_matches_one_step_bitwise(n, nx, ny):
+    fields, noise = c0_inputs(nx, ny, q=n * n, seed=3 * nx + ny)
+    ref = _wsolver(nx, ny, n, 0)
+    ref.set_fields(*fields, noise)
+    runs = []
+    for v in TWO:
+        s = _wsolver(nx, ny, n, v)
+        assert s.steps_per_launch() == 2
+        s.set_fields(*fields, noise)
+        runs.append(s)
+    for k in (1, 2, 3, 5, 8):  # cumulative 1, 3, 6, 11, 19 steps
+        ref.step(k)
+        want = _state(ref)
+        for v, s in zip(TWO, runs):
+            s.step(k)
+            got = _state(s)
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), (v, k)
+    for s in runs + [ref]:
+        s.close()
+
+
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("nx,ny", [(5, 3), (60, 17), (125, 40)])
+def test_walled_two_step_fp64_matches_one_step_bitwise(n, nx, ny):
+    fields, noise = c0_inputs(nx, ny, q=n * n, seed=nx + 7)
+    a, b = _wsolver(nx, ny, n, 0, "f64"), _wsolver(nx, ny, n, 22, "f64")
+    assert b.steps_per_launch() == 2
+    for s in (a, b):
+        s.set_fields(*fields, noise)
+    for k in (1, 4, 7):
+        a.step(k), b.step(k)
+        for x, y in zip(_state(a), _state(b)):
+            assert np.array_equal(x, y), k
+    a.close(), b.close()
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(4, "f32", 1e-5), (4, "f64", 1e-12), (6, "f32", 1e-5)])
+def test_walled_two_step_against_the_oracle(n, dtype, tol):
+    """Walled 131 x 45 grid, 21 steps (10 two-step launches and a single
+    step), against the FP64 oracle; mass conserved by the walls."""
+    nx, ny, K = 131, 45, 21
+    s, g = make_pair(nx, ny, n=n, dtype=dtype, tau=0.6, variant=22, **WALLS)
+    assert s.steps_per_launch() == 2
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    noise = inputs.population_noise(n * n, ny, nx, amp=1e-4, seed=12)
+    s.set_fields(*fields, noise)
+    _, t0 = s.moments()
+    s.step(K)
+    _, t1 = s.moments()
+    fr = g.run(g.set_fields(*fields, noise), K)
+    assert rel_inf(s.populations().cpu().numpy(), fr) <= tol
+    assert abs(t1[0] - t0[0]) / t0[0] <= (1e-13 if dtype == "f64" else 1e-6)
     s.close()
