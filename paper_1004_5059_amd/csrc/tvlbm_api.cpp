@@ -1130,18 +1130,33 @@ void make_items(const tvlbm_batch* b, ShapeOf shape_of, std::vector<Work>& all,
   start[b->inst.size()] = (int32_t)all.size();
 }
 
-// Work items of the two-step kernel: strips of Wg - 4 output columns with
-// two halo lanes each side (Wg = 32 lanes for instances up to 28 columns
-// wide, else 64), 64 / Wg consecutive segments of `rows` rows per item.
+// Strip width of the two-step kernel for an instance nx columns wide: w
+// output columns in a lane group of w + 4 lanes (two halo lanes each side),
+// 64 / (w + 4) groups per wavefront.  Picks the w that needs the fewest
+// lanes per row, ceil(nx / w) * 64 / G, the widest on ties (less halo).
+int strip2_width(int nx) {
+  int best_w = 60;
+  double best = 1e30;
+  for (int w = 60; w >= 4; --w) {
+    const int G = 64 / (w + 4);
+    const double lanes = (double)((nx + w - 1) / w) * 64.0 / G;
+    if (lanes < best - 1e-9) best = lanes, best_w = w;
+  }
+  return best_w;
+}
+
+// Work items of the two-step kernel: strips of w output columns (lane
+// groups of Wg = w + 4 lanes) and G = 64 / Wg consecutive segments of
+// `rows` rows per item, one per lane group.
 void make_items2(const tvlbm_batch* b, int rows, std::vector<Work>& all, std::vector<int32_t>& start) {
   all.clear();
   start.assign(b->inst.size() + 1, 0);
   for (size_t k = 0; k < b->inst.size(); ++k) {
     start[k] = (int32_t)all.size();
     const tvlbm_inst& I = b->inst[k];
-    const int wg = I.nx <= 28 ? 32 : 64, G = 64 / wg;
+    const int w = strip2_width(I.nx), wg = w + 4, G = 64 / wg;
     const int nseg = (I.ny + rows - 1) / rows;
-    for (int x0 = 0; x0 < I.nx; x0 += wg - 4)
+    for (int x0 = 0; x0 < I.nx; x0 += w)
       for (int sg = 0; sg < nseg; sg += G) all.push_back(Work{(int32_t)k, x0, sg, wg | (rows << 8)});
   }
   start[b->inst.size()] = (int32_t)all.size();

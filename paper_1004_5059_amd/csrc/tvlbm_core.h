@@ -35,6 +35,15 @@ constexpr double DIM = 2.0;
 // offset l * plane is a wave-uniform SGPR offset, so no per-load address
 // arithmetic is spent on the vector ALUs.  Accesses beyond the block return
 // zero instead of faulting.
+// Tables that no kernel writes while it reads them (instance parameters,
+// work items): read through the constant address space, so that reads at a
+// wave-uniform index become scalar loads, kept in SGPRs where they repeat.
+template <typename T>
+__device__ __forceinline__ const T& ro(const T* p, int i) {
+  using cT = const __attribute__((address_space(4))) T;
+  return *(const T*)((cT*)p + i);
+}
+
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);

@@ -648,19 +648,28 @@ __global__ __launch_bounds__(256) void k_march2(const MarchArgs<R> A) {
 //  * the first step on a wall row pulls the populations coming from beyond
 //    the wall from that wall's ghost of g^k (the re-emitted incident mass,
 //    eq.(IMPOSITION)), exactly as the one-step march does;
-//  * rows beyond a wall are not computed.  When an output row is a wall row
-//    whose upstream row lies beyond the wall, the second step takes the
-//    x-pulled ghost of g^{k+1} instead: the incident mass of the wall row's
-//    g^{k+1} per column (x-pulled values of this lane) and, for the ghost's
-//    own x-pull, of the neighbouring columns (DPP lane shifts).  The ghost's
-//    x-reach is two columns (incident x-pull, then emitted x-pull), so a
-//    strip carries two halo lanes on each side;
+//  * when an output row is a wall row whose upstream row lies beyond the
+//    wall, the second step takes the x-pulled ghost of g^{k+1} instead: the
+//    incident mass of the wall row's g^{k+1} per column (x-pulled values of
+//    this lane) and, for the ghost's own x-pull, of the neighbouring columns
+//    (DPP lane shifts).  The ghost's x-reach is two columns (incident x-pull,
+//    then emitted x-pull), so a strip carries two halo lanes on each side.
 // Every output cell sees the operations of two one-step launches in the
 // same order, so the result is bitwise that of the one-step march.
 //
+// A wavefront may hold several lane groups (row segments) whose wall rows
+// differ, so no branch depends on the lane: every group runs the same
+// first-step rows relative to its segment, rows beyond a wall or past the
+// segment included (their loads are clamped into the grid and their values
+// never reach a stored output), the ghosts are formed when any lane needs
+// them and taken per lane by selects, and only the stores are masked.  The
+// loads stay unconditional, so the compiler can issue them back to back.
+//
 // Per lane: segment [j0, j1) (live = the segment exists), its column
 // ic (im, ip: periodic neighbours), active = stores.  nt = uniform trip count
-// (rows per segment + 2).  Lanes of one segment share every branch below.
+// (rows per segment + 2).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 template <typename R, int N, int ORD, bool COMP, int DIR>
 __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Inst<R>& P, int ic,
                                                 int im, int ip, bool active, bool live, int j0,
@@ -676,40 +685,48 @@ __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Ins
   const int nout = j1 - j0;
   const int jf = DIR > 0 ? j0 : j1 - 1;  // first output row
   const int jl = DIR > 0 ? j1 - 1 : j0;  // last output row
-  // an output row at either end whose upstream row lies beyond a wall
-  const bool gh_first = DIR > 0 ? jf == 0 : jf == ny - 1;
-  const bool gh_last = DIR > 0 ? jl == ny - 1 : jl == 0;
-  const int t_first = gh_first ? 1 : 0;         // first-step rows computed: t_first..t_last
-  const int t_last = gh_last ? nout : nout + 1;
-  const int rf = jf + (t_first - 1) * DIR, rl = jf + (t_last - 1) * DIR;
-  // the first / last computed row is a wall row pulling from beyond it
-  const bool wall_first = DIR > 0 ? rf == 0 : rf == ny - 1;
-  const bool wall_last = DIR > 0 ? rl == ny - 1 : rl == 0;
+  const int wb = DIR > 0 ? 0 : ny - 1;   // wall row behind the march / ahead of it
+  const int wa = DIR > 0 ? ny - 1 : 0;
+  const int rb = wb - DIR, ra = wa + DIR;  // first rows beyond those walls
+  // output row at either end whose upstream row lies beyond a wall
+  const bool gh_first = live && jf == wb;
+  const bool gh_last = live && jl == wa;
+  auto row_at = [&](int r) {  // load offsets of row r, clamped into the grid
+    const int rc = r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r);
+    return row_off((uint32_t)rc * ld, ic, im, ip);
+  };
 
+  // before the first row r_0 = jf - DIR: lead populations need X^k of the
+  // row behind r_0 (a wall's ghost when that row lies beyond the wall),
+  // trail ones of r_0 itself
   R hp[Q];
-  if (live) {
-    R m_c = R(0), m_m = R(0), m_p = R(0);
-    if (wall_first) {
-      const uint32_t rw = (uint32_t)rf * ld;
-      m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, -DIR);
-      m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, -DIR);
-      m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, -DIR);
-    }
-    const RowOff ob = row_off((uint32_t)(rf - DIR) * ld, ic, im, ip);  // unused when wall_first
-    const RowOff of = row_off((uint32_t)rf * ld, ic, im, ip);
+  {
+    const bool gb = live && jf - 2 * DIR == rb;
+    const RowOff ob = row_at(jf - 2 * DIR);
+    const RowOff of = row_at(jf - DIR);
 #pragma unroll
     for (int a = 0; a < N; ++a) {
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         const int l = a * N + b;
         const int sg = node_sign<N>(b);
-        if (sg == DIR)
-          hp[l] = wall_first ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p)
-                             : xpull<R, N>(L, s, (uint32_t)(l * plane), a, ob);
-        else if (sg == -DIR)
-          hp[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, of);
-        else
-          hp[l] = R(0);
+        hp[l] = sg == 0 ? R(0) : xpull<R, N>(L, s, (uint32_t)(l * plane), a, sg == DIR ? ob : of);
+      }
+    }
+    if (wave_any(gb)) {
+      // (loaded, not taken from the neighbouring lanes: with the ghost of
+      // g^(k+1) that also takes its neighbours' masses, the reach would
+      // exceed the two halo lanes)
+      const uint32_t rw = (uint32_t)wb * ld;
+      const R m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, -DIR);
+      const R m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, -DIR);
+      const R m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, -DIR);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == DIR)
+            hp[a * N + b] = gb ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p) : hp[a * N + b];
       }
     }
   }
@@ -719,67 +736,92 @@ __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Ins
   for (int l = 0; l < Q; ++l) y1[l] = y2[l] = R(0);
   for (int t = 0; t < nt; ++t) {
     const int r = jf + (t - 1) * DIR;
-    R x[Q];
-    if (live && t >= t_first && t <= t_last) {
-      // first step on row r
-      const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
-      const bool ghost_next = wall_last && t == t_last;  // row r + DIR beyond a wall
-      R m_c = R(0), m_m = R(0), m_p = R(0);
-      if (ghost_next) {
-        const uint32_t rw = (uint32_t)r * ld;
-        m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, DIR);
-        m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, DIR);
-        m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, DIR);
+    // first step on row r: lead populations pull rows r and r - DIR, trail
+    // ones rows r and r + DIR; a row beyond a wall is that wall's ghost
+    const bool glead = r == rb;         // row r lies beyond the wall behind
+    const bool gtrail = r + DIR == ra;  // row r + DIR lies beyond the wall ahead
+    const RowOff oj = row_at(r);
+    const RowOff on = row_at(r + DIR);
+    R hn[Q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        hn[l] = xpull<R, N>(L, s, (uint32_t)(l * plane), a, node_sign<N>(b) == -DIR ? on : oj);
       }
-      const RowOff on = row_off((uint32_t)(r + DIR) * ld, ic, im, ip);
-      R d[Q];
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          const int l = a * N + b;
-          const int sg = node_sign<N>(b);
-          const uint32_t pl = (uint32_t)(l * plane);
-          if (sg == DIR) {  // lead
-            const R hn = xpull<R, N>(L, s, pl, a, oj);
-            d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
-            hp[l] = hn;
-          } else if (sg == -DIR) {  // trail
-            const R hn = ghost_next ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p)
-                                    : xpull<R, N>(L, s, pl, a, on);
-            d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
-            hp[l] = hn;
-          } else {
-            d[l] = xpull<R, N>(L, s, pl, a, oj);
-          }
-        }
-      }
-      R g[Q];
-      collide_regs<R, N, ORD, COMP>(L, P, d, g);
-      // x part of the second remap: upstream column from the neighbouring
-      // lane (lanes of this segment all take this branch; a neighbour in
-      // another segment is a halo lane's, whose results are not stored)
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        const int sa = node_sign<N>(a);
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          const int l = a * N + b;
-          if (sa > 0)
-            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
-          else if (sa < 0)
-            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
-          else
-            x[l] = g[l];
-        }
-      }
-    } else {
-      // no row here (beyond a wall, or past the segment): placeholder values
-      // that no output uses (the trail ones are replaced by a ghost below)
-#pragma unroll
-      for (int l = 0; l < Q; ++l) x[l] = y1[l];
     }
-    if (live && gh_first && t == 1) {
+    if (wave_any(live && glead)) {
+      // (loaded, not taken from the neighbouring lanes: with the ghost of
+      // g^(k+1) that also takes its neighbours' masses, the reach would
+      // exceed the two halo lanes)
+      const uint32_t rw = (uint32_t)wb * ld;
+      const R m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, -DIR);
+      const R m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, -DIR);
+      const R m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, -DIR);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == DIR)
+            hn[a * N + b] = glead ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p) : hn[a * N + b];
+      }
+    }
+    if (wave_any(live && gtrail)) {
+      // (loaded, not taken from the neighbouring lanes: with the ghost of
+      // g^(k+1) that also takes its neighbours' masses, the reach would
+      // exceed the two halo lanes)
+      const uint32_t rw = (uint32_t)wa * ld;
+      const R m_c = wall_mass<R, N>(L, s, plane, rw, ic, nx, DIR);
+      const R m_m = wall_mass<R, N>(L, s, plane, rw, im, nx, DIR);
+      const R m_p = wall_mass<R, N>(L, s, plane, rw, ip, nx, DIR);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == -DIR)
+            hn[a * N + b] = gtrail ? ghost_of<R, N>(L, P, a, b, m_c, m_m, m_p) : hn[a * N + b];
+      }
+    }
+    R d[Q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        const int sg = node_sign<N>(b);
+        if (sg == DIR) {  // lead
+          d[l] = fmaR(L.qm[b], hn[l], L.p[b] * hp[l]);
+          hp[l] = hn[l];
+        } else if (sg == -DIR) {  // trail
+          d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn[l]);
+          hp[l] = hn[l];
+        } else {
+          d[l] = hn[l];
+        }
+      }
+    }
+    R g[Q];
+    collide_regs<R, N, ORD, COMP>(L, P, d, g);
+    // x part of the second remap: upstream column from the neighbouring
+    // lane (a neighbour in another lane group is a halo lane's, whose
+    // results are not stored)
+    R x[Q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const int sa = node_sign<N>(a);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int l = a * N + b;
+        if (sa > 0)
+          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
+        else if (sa < 0)
+          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
+        else
+          x[l] = g[l];
+      }
+    }
+    if (t == 1 && wave_any(gh_first)) {
       // ghost of g^{k+1} behind the first output row (a wall row): mass its
       // populations carry through that wall, re-emitted into the lead ones
       R m = R(0);
@@ -796,10 +838,12 @@ __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Ins
       for (int a = 0; a < N; ++a) {
 #pragma unroll
         for (int b = 0; b < N; ++b)
-          if (node_sign<N>(b) == DIR) y1[a * N + b] = ghost_of<R, N>(L, P, a, b, m, m_m, m_p);
+          if (node_sign<N>(b) == DIR)
+            y1[a * N + b] = gh_first ? ghost_of<R, N>(L, P, a, b, m, m_m, m_p) : y1[a * N + b];
       }
     }
-    if (live && gh_last && t == nout + 1) {
+    const bool gl_now = gh_last && t == nout + 1;
+    if (wave_any(gl_now)) {
       // ghost of g^{k+1} beyond the last output row (a wall row), from that
       // row's x-pulled g^{k+1} (in y1), re-emitted into the trail populations
       R m = R(0);
@@ -816,11 +860,11 @@ __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Ins
       for (int a = 0; a < N; ++a) {
 #pragma unroll
         for (int b = 0; b < N; ++b)
-          if (node_sign<N>(b) == -DIR) x[a * N + b] = ghost_of<R, N>(L, P, a, b, m, m_m, m_p);
+          if (node_sign<N>(b) == -DIR)
+            x[a * N + b] = gl_now ? ghost_of<R, N>(L, P, a, b, m, m_m, m_p) : x[a * N + b];
       }
     }
-    if (live && t >= 2 && t <= nout + 1) {  // second step on output row r - DIR
-      const int mrow = r - DIR;
+    if (t >= 2) {  // second step on output row r - DIR
       R e[Q];
 #pragma unroll
       for (int a = 0; a < N; ++a) {
@@ -838,8 +882,8 @@ __device__ __forceinline__ void march2_wall_seg(const MarchArgs<R>& A, const Ins
       }
       R g2[Q];
       collide_regs<R, N, ORD, COMP>(L, P, e, g2);
-      if (active) {
-        const uint32_t om = (uint32_t)mrow * ld + (uint32_t)ic;
+      if (active && t <= nout + 1) {
+        const uint32_t om = (uint32_t)(r - DIR) * ld + (uint32_t)ic;
 #pragma unroll
         for (int l = 0; l < Q; ++l) bst(dst, om, (uint32_t)(l * plane), g2[l]);
       }
@@ -888,11 +932,12 @@ __global__ __launch_bounds__(256) void k_march2w(const MarchArgs<R> A) {
 
 // Batched walled channels, two steps per launch: persistent grid-stride
 // over the live work list as k_march_batch.  An item is one strip of an
-// instance (Wg - 4 output columns, two halo lanes each side, Wg = 32 or 64
-// lanes) and 64 / Wg consecutive row segments, one per lane group; the
-// groups of a wavefront march in the same direction.  A chunk of steps ends
-// with single-step launches (the library's state semantics: the other
-// buffer holds g^{k-1}), which also do the check mode.
+// instance (Wg - 4 output columns, two halo lanes each side, 5 <= Wg <= 64
+// lanes) and G = 64 / Wg consecutive row segments, one per lane group
+// (lanes past G Wg idle); the groups of a wavefront march in the same
+// direction.  A chunk of steps ends with single-step launches (the
+// library's state semantics: the other buffer holds g^{k-1}), which also do
+// the check mode.
 template <typename R, int N, int ORD, bool COMP>
 __global__ __launch_bounds__(256) void k_march2_batch(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
@@ -907,14 +952,14 @@ __global__ __launch_bounds__(256) void k_march2_batch(const MarchArgs<R> A) {
     stride = (int)(gridDim.x >> 3) * 4;
   }
   for (int w = first; w < hi; w += stride) {
-    const Work it = A.work[w];
-    const Inst<R>& P = A.insts[it.inst];
+    const Work it = ro(A.work, w);
+    const Inst<R>& P = ro(A.insts, it.inst);
     const int Wg = it.shape & 0xff, rows = (it.shape >> 8) & 0xff;
     const int G = 64 / Wg;
-    const int gl = lane & (Wg - 1), g = lane / Wg;
+    const int g = lane / Wg, gl = lane - g * Wg;
     const int seg = it.seg0 + g;
     const int j0 = seg * rows;
-    const bool live = j0 < P.ny;
+    const bool live = g < G && j0 < P.ny;
     const int j1 = min(j0 + rows, P.ny);
     const int nx = P.nx;
     const int col = it.x0 - 2 + gl;
@@ -1068,8 +1113,8 @@ __global__ __launch_bounds__(256) void k_march_batch(const MarchArgs<R> A) {
     stride = (int)(gridDim.x >> 3) * 4;
   }
   for (int w = first; w < hi; w += stride) {
-    const Work it = A.work[w];
-    const Inst<R>& P = A.insts[it.inst];
+    const Work it = ro(A.work, w);
+    const Inst<R>& P = ro(A.insts, it.inst);
     const int W = it.shape & 0xff, rows = it.shape >> 8;
     const int i = it.x0 + (lane & (W - 1));
     const int seg = it.seg0 + lane / W;
@@ -1251,12 +1296,13 @@ __global__ __launch_bounds__(256) void k_mass_fix(R* __restrict__ g, const Inst<
   const long long dmi = (long long)(ref[b] - cur[b]);
   if (dmi == 0) return;
   const R delta = (R)((double)dmi / MASS_FP_SCALE / area[b]);
-  const int64_t n = (int64_t)P.nx * P.ny;
-  const int64_t k0 = n * sl / RESID_SLICES, k1 = n * (sl + 1) / RESID_SLICES;
-  for (int64_t c = k0 + threadIdx.x; c < k1; c += 256) {
-    const int64_t j = c / P.nx, i = c % P.nx;
-    R* p = g + P.off + j * P.ld + i;
-    for (int l = 0; l < q; ++l) p[l * P.plane] = fmaR(L.w[l], delta, p[l * P.plane]);
+  const int64_t n = (int64_t)P.nx * P.ny;  // < 2^31 (a plane is 32-bit addressed)
+  const int k0 = (int)(n * sl / RESID_SLICES), k1 = (int)(n * (sl + 1) / RESID_SLICES);
+  const uint32_t nx = (uint32_t)P.nx;
+  for (int c = k0 + (int)threadIdx.x; c < k1; c += 256) {
+    const uint32_t j = (uint32_t)c / nx, i = (uint32_t)c - j * nx;
+    R* p = g + P.off + (int64_t)j * P.ld + i;
+    for (int l = 0; l < q; ++l, p += P.plane) *p = fmaR(L.w[l], delta, *p);
   }
 }
 
