@@ -617,8 +617,12 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
 }
 
 // One workgroup = 4 wavefronts = 4 consecutive row segments of one strip.
+// At least two wavefronts per SIMD: the D2Q36 form would otherwise take a
+// few registers past half the file and run one wavefront per SIMD, with no
+// other to hide its load latency; the few values spilled under the bound
+// cost less than that (the smaller lattices fit anyway).
 template <typename R, int N, int ORD, bool COMP>
-__global__ __launch_bounds__(256) void k_march2(const MarchArgs<R> A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march2(const MarchArgs<R> A) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nb = gridDim.x;  // multiple of 8
