@@ -343,6 +343,50 @@ def run_c2(tol: float = 1e-8, k: int = 100):
             "kernel": "k_rows (non-uniform rows, diffuse walls)"}
 
 
+def run_c4(n_train: int = 4096, n_test: int = 256, epochs: int = 40, batch: int = 32,
+           lr: float = 2e-3, gen_start: str = "closed_form", tol: float = 1e-8):
+    """Learned warm start: training states from batched steady solves of the
+    thermal-Couette sampler (seed 2026), the bf16-MFMA network trained on
+    them (residual from the closed-form profile), then the held-out
+    instances (seed 2027) solved from the uniform start, from the
+    closed-form profile and from the network's prediction (inference
+    included, fallback re-solves counted).  The training solves start from
+    the closed-form profile by default (about 4x fewer steps than from
+    uniform; the states agree to what the stopping rule leaves)."""
+    import numpy as np
+    import torch
+
+    from paper_1004_5059_amd import inputs, warmstart as ws
+    from paper_1004_5059_amd.autotune import autotune_batch
+    from paper_1004_5059_amd.tvlbm import TvNet
+
+    H, W = 256, 128
+    tune = autotune_batch(inputs.couette_instances(256, seed=2026))
+    quiet = lambda msg: None  # noqa: E731
+    t0 = time.perf_counter()
+    tr, prof, steps = ws.generate(n_train, seed=2026, log=quiet, tune=tune, start=gen_start,
+                                  tol=tol)
+    t_gen = time.perf_counter() - t0
+    param = ws.make_param(tr, prof, residual=True)
+    net = TvNet(ws.C_IN, H, W, max_batch=batch)
+    net.set_params(ws.init_params(ws.C_IN, seed=0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ws.train(net, tr, prof, H, W, epochs=epochs, batch=batch, lr=lr, log=quiet, param=param)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    te = inputs.couette_instances(n_test, seed=2027)
+    res = ws.warm_vs_uniform(net, te, H, W, tol=tol, log=quiet, tune=tune, param=param)
+    net.close()
+    res.pop("fallback_instances")
+    out = {"n_train": n_train, "n_test": n_test, "train_seed": 2026, "test_seed": 2027,
+           "epochs": epochs, "data_generation_start": gen_start,
+           "data_generation_s": round(t_gen, 2), "train_steps_mean": float(np.mean(steps)),
+           "training_s": round(t_train, 2), "final_loss": hist[-1]}
+    out.update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()})
+    return out
+
+
 def cpu_baseline(size: int, target_s: float = 15.0):
     """The FP64 oracle, as it stands, on this host's cores: a bounded sample
     (a few steps of the same 1024^2 D2Q16 workload)."""
@@ -400,6 +444,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched steady-solve leg")
     ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume legs")
     ap.add_argument("--no-c2", action="store_true", help="skip the bounded-flow steady solve")
+    ap.add_argument("--no-c4", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--fv-only", action="store_true", help="run only the finite-volume legs")
     ap.add_argument("--fv-size", type=int, default=1024, help="mesh size of the finite-volume legs")
     ap.add_argument("--batched-load-only", action="store_true",
@@ -454,6 +499,7 @@ def main():
     bat = None if args.no_batched else leg("batched", run_batched, 256, 2, 1e-8, 100,
                                            not args.batched_load_only)
     c2 = None if args.no_c2 else leg("C2 bounded flow", run_c2)
+    c4 = None if args.no_c4 else leg("C4 warm start", run_c4)
     cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
     achieved = r16["achieved_gbs"]
     prof = counters_from_profile(r16["steps_per_launch"], r16["variant"])
@@ -517,6 +563,7 @@ def main():
         "c0_64x64_f64": c0,
         "copy_ceiling_gbs": None if cp is None else round(cp["gbs"], 1),
         "c2_bounded_flow": c2,
+        "c4_warm_start": c4,
         "batched": bat,
         "finite_volume": fv,
     }

@@ -245,11 +245,15 @@ int tvlbm_batch_set_fields(tvlbm_batch *b, const void *fields);
  * is below tol or it has taken max_steps.  FP32: as tvlbm_solve, the
  * starting mass of every instance that goes on is put back at each check.  steps_out (host, n_inst) gets the
  * steps each instance took, r_out (host, n_inst, may be NULL) its last
- * residual.  Synchronises.  ENOTCONVERGED if any instance hit max_steps. */
+ * residual.  Synchronises.  ENOTCONVERGED if any instance hit max_steps.
+ * An instance whose state goes non-finite stops at the next check with a
+ * NaN residual and the others run on to their own ends; the call then
+ * returns ENONFINITE, with steps_out and r_out filled for every instance. */
 int tvlbm_batch_run(tvlbm_batch *b, int64_t max_steps, double tol,
                     int32_t k_interval, int64_t *steps_out, double *r_out);
 /* Fields of every instance's current state into fields_out (device, packed);
- * synchronises; ENONFINITE as tvlbm_moments. */
+ * synchronises; ENONFINITE as tvlbm_moments (fields_out is written first,
+ * so the finite instances' fields are still usable). */
 int tvlbm_batch_fields(tvlbm_batch *b, void *fields_out);
 /* Launch shape for instances with nx <= max_nx (size class): wavefront strip
  * width (16, 32 or 64 columns) and rows per lane segment.  Results do not

@@ -472,16 +472,24 @@ def tvlbm_batch_set_fields(h, fields):
 
 
 def tvlbm_batch_run(h, n_inst: int, max_steps: int, tol: float, k_interval: int = 100):
+    """(ok, steps, r): ok when every instance reached tol.  An instance that
+    hit max_steps keeps its last residual; one whose state went non-finite
+    (stopped at that check) has r = nan.  Other errors raise."""
     steps = (ctypes.c_int64 * n_inst)()
     r = (ctypes.c_double * n_inst)()
     rc = lib().tvlbm_batch_run(h, int(max_steps), float(tol), int(k_interval), steps, r)
-    if rc not in (TVLBM_OK, TVLBM_ENOTCONVERGED):
+    if rc not in (TVLBM_OK, TVLBM_ENOTCONVERGED, TVLBM_ENONFINITE):
         raise TvlbmError(rc, "batch run")
     return rc == TVLBM_OK, np.array(steps[:]), np.array(r[:])
 
 
-def tvlbm_batch_fields(h, out):
-    _check(lib().tvlbm_batch_fields(h, _ptr(out)))
+def tvlbm_batch_fields(h, out, allow_nonfinite: bool = False):
+    """allow_nonfinite: fill out even when some instance's fields are not
+    finite (instead of raising ENONFINITE)."""
+    rc = lib().tvlbm_batch_fields(h, _ptr(out))
+    if rc == TVLBM_ENONFINITE and allow_nonfinite:
+        return
+    _check(rc)
 
 
 def tvlbm_batch_set_shape(h, max_nx: int, width: int, rows: int):
@@ -596,13 +604,15 @@ class BatchSolver:
     def run(self, max_steps: int, tol: float = 1e-8, k_interval: int = 100):
         return tvlbm_batch_run(self.h, self.n, max_steps, tol, k_interval)
 
-    def fields_packed(self):
+    def fields_packed(self, allow_nonfinite: bool = False):
         out = self.torch.empty(self.field_elems, dtype=self.tdtype, device=self.device)
-        tvlbm_batch_fields(self.h, out)
+        tvlbm_batch_fields(self.h, out, allow_nonfinite)
         return out
 
-    def fields(self):
-        flat = self.fields_packed().double().cpu().numpy()
+    def fields(self, allow_nonfinite: bool = False):
+        """Per-instance [4][ny][nx] fields; allow_nonfinite: return them even
+        if some instance went non-finite (its arrays then hold nan/inf)."""
+        flat = self.fields_packed(allow_nonfinite).double().cpu().numpy()
         return [flat[self.fld_off[k]:self.fld_off[k + 1]].reshape(4, ny, nx)
                 for k, (nx, ny) in enumerate(self.shapes)]
 

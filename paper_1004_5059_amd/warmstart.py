@@ -143,18 +143,31 @@ def solve_batch(insts, fields=None, max_steps=2_000_000, tol=1e-8, k=100, dtype=
     t0 = time.perf_counter()
     ok, steps, r = b.run(max_steps, tol, k)
     dt = time.perf_counter() - t0
-    prof = [f[:, :, 0] for f in b.fields()]
+    # an instance that went non-finite has r = nan and nan fields; the
+    # others are unaffected (the caller decides what to do with it)
+    prof = [f[:, :, 0] for f in b.fields(allow_nonfinite=True)]
     b.close()
     return steps, r, prof, dt
 
 
-def generate(n: int, seed: int, batch: int = 256, log=print, **kw):
-    """Steady states of n sampled channels, solved in batches of `batch`."""
+def generate(n: int, seed: int, batch: int = 256, log=print, start: str = "uniform", **kw):
+    """Steady states of n sampled channels, solved in batches of `batch`.
+
+    start: "uniform" (rho = 1, u = 0, T = 1) or "closed_form" (the
+    closed-form thermal-Couette profile, about 4x fewer steps to the same
+    tolerance; the converged states then differ from the uniform start's
+    by what the stopping rule leaves, ~1e-3)."""
+    if start not in ("uniform", "closed_form"):
+        raise ValueError(f"start must be 'uniform' or 'closed_form', not {start!r}")
     insts = inputs.couette_instances(n, seed=seed)
     profiles, steps = [], []
     for s in range(0, n, batch):
         chunk = insts[s:s + batch]
-        st, r, prof, dt = solve_batch(chunk, **kw)
+        fields = closed_form_fields(chunk) if start == "closed_form" else None
+        st, r, prof, dt = solve_batch(chunk, fields=fields, **kw)
+        if not np.all(r < kw.get("tol", 1e-8)):
+            raise RuntimeError(f"data generation: {int(np.sum(~(r < kw.get('tol', 1e-8))))} "
+                               "instances did not converge")
         profiles += prof
         steps += list(st)
         log(f"generated {s + len(chunk)}/{n} steady states ({dt:.1f} s, max steps {int(np.max(st))})")
@@ -209,10 +222,16 @@ def init_params(c_in: int, seed: int = 0):
 
 
 def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, tune=None,
-                    param=None):
+                    param=None, warm_max_steps=None):
     """Solve the same instances from the uniform start, from the closed-form
     profile and from the network's prediction (inference time included);
-    returns a summary dict."""
+    returns a summary dict.
+
+    Fallback: a warm-started instance that does not reach tol within
+    warm_max_steps (default max_steps) or goes non-finite is solved again
+    from the uniform start (its steps and time are added to the warm
+    totals), so every instance ends at the steady state the uniform start
+    reaches."""
     import torch
 
     st_u, r_u, prof_u, t_u = solve_batch(insts, max_steps=max_steps, tol=tol, tune=tune)
@@ -223,12 +242,13 @@ def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, 
     y = predict(net, insts, H, W)
     fields = predicted_fields(insts, y, param)
     t_inf = time.perf_counter() - t0
-    st_w, r_w, prof_w, t_w = solve_batch(insts, fields=fields, max_steps=max_steps, tol=tol, tune=tune)
+    wmax = max_steps if warm_max_steps is None else warm_max_steps
+    st_w, r_w, prof_w, t_w = solve_batch(insts, fields=fields, max_steps=wmax, tol=tol, tune=tune)
     bad = [k for k in range(len(insts)) if not (r_w[k] < tol) or not np.all(np.isfinite(prof_w[k]))]
     t_fb = 0.0
     if bad:
         sub = [insts[k] for k in bad]
-        st_f, r_f, prof_f, t_fb = solve_batch(sub, max_steps=max_steps, tol=tol)
+        st_f, r_f, prof_f, t_fb = solve_batch(sub, max_steps=max_steps, tol=tol, tune=tune)
         for j, k in enumerate(bad):
             st_w[k] += st_f[j]
             prof_w[k] = prof_f[j]
@@ -242,13 +262,14 @@ def warm_vs_uniform(net, insts, H, W, max_steps=2_000_000, tol=1e-8, log=print, 
         cf = closed_form_profile(d)
         cf_err.append(float(np.max(np.abs(cf[1] - prof_u[k][1])) / max(d["u_top"], 1e-3)))
     out = {
-        "n": len(insts),
+        "n": len(insts), "fallback_instances": bad,
         "uniform_steps_mean": float(np.mean(st_u)), "warm_steps_mean": float(np.mean(st_w)),
         "uniform_steps_max": int(np.max(st_u)), "warm_steps_max": int(np.max(st_w)),
         "uniform_wall_s": t_u, "warm_wall_s": t_w + t_inf + t_fb, "inference_s": t_inf,
         "fallbacks": len(bad), "steady_field_maxdiff": float(np.max(err)),
-        "pred_u_err_rel_median": float(np.median(pred_err)),
-        "pred_T_err_rel_median": float(np.median(pred_err_T)),
+        # (nanmedian: a prediction that is not finite is a fallback case)
+        "pred_u_err_rel_median": float(np.nanmedian(pred_err)),
+        "pred_T_err_rel_median": float(np.nanmedian(pred_err_T)),
         "closed_form_u_err_rel_median": float(np.median(cf_err)),
         "closed_form_steps_mean": float(np.mean(st_c)), "closed_form_steps_max": int(np.max(st_c)),
         "closed_form_wall_s": t_c, "closed_form_converged": bool(np.all(r_c < tol)),
@@ -272,6 +293,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default="warmstart_result.json")
+    ap.add_argument("--gen-start", choices=["uniform", "closed_form"], default="uniform",
+                    help="start of the training-data solves")
     ap.add_argument("--absolute", action="store_true",
                     help="predict the fields themselves instead of the residual from the "
                          "closed-form profile")
@@ -283,7 +306,7 @@ def main(argv=None):
     tune = autotune_batch(inputs.couette_instances(256, seed=2026))
     log(f"batch tuning: {tune}")
     t0 = time.perf_counter()
-    tr, prof, steps = generate(a.n_train, seed=2026, log=log, tune=tune)
+    tr, prof, steps = generate(a.n_train, seed=2026, log=log, tune=tune, start=a.gen_start)
     t_gen = time.perf_counter() - t0
     param = make_param(tr, prof, residual=not a.absolute)
     log(f"output parametrisation: residual={param['residual']} scale={param['scale'].tolist()}")
@@ -298,7 +321,8 @@ def main(argv=None):
     res = warm_vs_uniform(net, te, H, W, log=log, tune=tune, param=param)
     res.update({"data_generation_s": t_gen, "training_s": t_train, "n_train": a.n_train,
                 "epochs": a.epochs, "final_loss": hist[-1], "train_steps_mean": float(np.mean(steps)),
-                "residual": param["residual"], "out_scale": param["scale"].tolist()})
+                "residual": param["residual"], "out_scale": param["scale"].tolist(),
+                "data_generation_start": a.gen_start})
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)
