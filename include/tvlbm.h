@@ -171,9 +171,26 @@ int tvlbm_lattice(const tvlbm_ctx *ctx, double *xi, double *w, double *shift,
 int tvlbm_lattice_table(int32_t n_gh, int32_t eq_order, double cfl, int32_t cfl_norm,
                         double *xi, double *w, double *shift, double *lambda);
 
-/* Checkpoint: header + raw state; tvlbm_load needs an identical descriptor. */
+/* Checkpoint: a TVLBM_CKPT_HEADER_BYTES header, then the raw state (g^k,
+ * then the other buffer, q*ny*ld elements each).  The header (format 2,
+ * magic "TVLBMCK2") records every descriptor field that fixes a step's
+ * arithmetic: n_gh, eq_order, dtype, nx, ny, y_bc, collide, cfl_norm,
+ * compensated (as used: 0 for F64), ld (as used), tau, cfl, the wall
+ * velocities and temperatures (recorded as 0 for periodic grids) and an
+ * FNV-1a 64-bit hash of the row heights (0 for unit rows), plus the step
+ * count.  tvlbm_load restores the state and step count and returns EIO,
+ * naming the first differing field in tvlbm_last_error, unless the
+ * context's header would be identical (format-1 files are refused). */
+#define TVLBM_CKPT_HEADER_BYTES 128
 int tvlbm_save(tvlbm_ctx *ctx, const char *path);
 int tvlbm_load(tvlbm_ctx *ctx, const char *path);
+/* Host only (no device work): the header tvlbm_save would write for a
+ * context built from desc at step `step` (out: host, >= out_bytes =
+ * TVLBM_CKPT_HEADER_BYTES), and the check tvlbm_load applies to a header
+ * read from a file (EIO on any difference; *step, may be NULL, gets the
+ * stored step count). */
+int tvlbm_ckpt_header(const tvlbm_desc *desc, int64_t step, void *out, int64_t out_bytes);
+int tvlbm_ckpt_check(const void *header, int64_t bytes, const tvlbm_desc *desc, int64_t *step);
 
 /* Launch-shape variant of the fused step kernel (rows per wavefront and
  * waves per workgroup); all variants compute identical results, bit for

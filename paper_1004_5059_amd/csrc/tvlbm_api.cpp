@@ -924,22 +924,89 @@ int tvlbm_set_variant(tvlbm_ctx* c, int32_t v) {
   return TVLBM_OK;
 }
 
+// Checkpoint header, format 2: every descriptor field that fixes the
+// arithmetic of a step, so that a state resumes only under the same update.
+// Wall data are recorded as zero for periodic grids (they take no part).
 struct CkptHeader {
-  char magic[8];
-  int32_t version, n_gh, eq_order, dtype, nx, ny, y_bc, collide;
+  char magic[8];  // "TVLBMCK2"
+  int32_t version;
+  int32_t n_gh, eq_order, dtype, nx, ny, y_bc, collide, cfl_norm, compensated;
+  int32_t pad;
   int64_t ld, step;
   double tau, cfl;
+  double wall_lo_ux, wall_lo_T, wall_hi_ux, wall_hi_T;
+  uint64_t rows_hash;  // FNV-1a (64-bit) of the ny row heights' bytes; 0 = unit rows
 };
+static_assert(sizeof(CkptHeader) == TVLBM_CKPT_HEADER_BYTES, "checkpoint header layout");
+
+static uint64_t rows_hash(const double* dy, int32_t ny) {
+  if (!dy) return 0;
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* p = (const unsigned char*)dy;
+  for (size_t i = 0; i < sizeof(double) * (size_t)ny; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// header of a context built from d (dy: its row heights, or null)
+static CkptHeader make_header(const tvlbm_desc& d, const double* dy, int64_t step) {
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, "TVLBMCK2", 8);
+  h.version = 2;
+  h.n_gh = d.n_gh; h.eq_order = d.eq_order; h.dtype = d.dtype; h.nx = d.nx; h.ny = d.ny;
+  h.y_bc = d.y_bc; h.collide = d.collide; h.cfl_norm = d.cfl_norm;
+  h.compensated = d.dtype == TVLBM_F64 ? 0 : (d.compensated != 0);
+  h.ld = d.ld ? d.ld : ceil_div(d.nx, 64) * 64;
+  h.step = step;
+  h.tau = d.tau; h.cfl = d.cfl;
+  if (d.y_bc == TVLBM_BC_DIFFUSE_WALLS) {
+    h.wall_lo_ux = d.wall_lo_ux; h.wall_lo_T = d.wall_lo_T;
+    h.wall_hi_ux = d.wall_hi_ux; h.wall_hi_T = d.wall_hi_T;
+  }
+  h.rows_hash = rows_hash(dy, d.ny);
+  return h;
+}
+
+// first field in which a stored header differs from `want`, or null
+static const char* header_mismatch(const CkptHeader& h, const CkptHeader& want) {
+  if (std::memcmp(h.magic, "TVLBMCK1", 8) == 0)
+    return "format 1 checkpoint (no cfl_norm, wall or row-height record)";
+  if (std::memcmp(h.magic, "TVLBMCK2", 8) != 0 || h.version != 2) return "not a checkpoint of format 2";
+#define TVLBM_CKPT_FIELD(f) \
+  if (std::memcmp(&h.f, &want.f, sizeof h.f) != 0) return #f;
+  TVLBM_CKPT_FIELD(n_gh) TVLBM_CKPT_FIELD(eq_order) TVLBM_CKPT_FIELD(dtype) TVLBM_CKPT_FIELD(nx)
+  TVLBM_CKPT_FIELD(ny) TVLBM_CKPT_FIELD(y_bc) TVLBM_CKPT_FIELD(collide) TVLBM_CKPT_FIELD(cfl_norm)
+  TVLBM_CKPT_FIELD(compensated) TVLBM_CKPT_FIELD(ld) TVLBM_CKPT_FIELD(tau) TVLBM_CKPT_FIELD(cfl)
+  TVLBM_CKPT_FIELD(wall_lo_ux) TVLBM_CKPT_FIELD(wall_lo_T) TVLBM_CKPT_FIELD(wall_hi_ux)
+  TVLBM_CKPT_FIELD(wall_hi_T) TVLBM_CKPT_FIELD(rows_hash)
+#undef TVLBM_CKPT_FIELD
+  return nullptr;
+}
+
+int tvlbm_ckpt_header(const tvlbm_desc* desc, int64_t step, void* out, int64_t out_bytes) {
+  if (!desc || !out || out_bytes < (int64_t)sizeof(CkptHeader)) return TVLBM_EINVAL;
+  const CkptHeader h = make_header(*desc, desc->dy, step);
+  std::memcpy(out, &h, sizeof h);
+  return TVLBM_OK;
+}
+
+int tvlbm_ckpt_check(const void* header, int64_t bytes, const tvlbm_desc* desc, int64_t* step) {
+  if (!header || !desc) return TVLBM_EINVAL;
+  if (bytes < (int64_t)sizeof(CkptHeader)) return TVLBM_EIO;
+  CkptHeader h;
+  std::memcpy(&h, header, sizeof h);
+  if (header_mismatch(h, make_header(*desc, desc->dy, 0))) return TVLBM_EIO;
+  if (step) *step = h.step;
+  return TVLBM_OK;
+}
 
 int tvlbm_save(tvlbm_ctx* c, const char* path) {
   if (!c || !path) return TVLBM_EINVAL;
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
-  CkptHeader h;
-  std::memset(&h, 0, sizeof h);
-  std::memcpy(h.magic, "TVLBMCK1", 8);
-  h.version = 1; h.n_gh = c->d.n_gh; h.eq_order = c->d.eq_order; h.dtype = c->d.dtype;
-  h.nx = c->d.nx; h.ny = c->d.ny; h.y_bc = c->d.y_bc; h.collide = c->d.collide;
-  h.ld = c->ld; h.step = c->step; h.tau = c->d.tau; h.cfl = c->d.cfl;
+  const CkptHeader h = make_header(c->d, c->rows ? c->dyh.data() : nullptr, c->step);
   const size_t bytes = (size_t)c->hl.q * c->plane * esize(c);
   std::vector<char> host(bytes);
   FILE* fp = std::fopen(path, "wb");
@@ -962,12 +1029,13 @@ int tvlbm_load(tvlbm_ctx* c, const char* path) {
   FILE* fp = std::fopen(path, "rb");
   if (!fp) return fail(c, TVLBM_EIO, "open for read");
   CkptHeader h;
-  if (std::fread(&h, sizeof h, 1, fp) != 1 || std::memcmp(h.magic, "TVLBMCK1", 8) != 0 || h.version != 1 ||
-      h.n_gh != c->d.n_gh || h.eq_order != c->d.eq_order || h.dtype != c->d.dtype || h.nx != c->d.nx ||
-      h.ny != c->d.ny || h.ld != c->ld || h.y_bc != c->d.y_bc || h.tau != c->d.tau || h.cfl != c->d.cfl ||
-      h.collide != c->d.collide) {
+  if (std::fread(&h, sizeof h, 1, fp) != 1) {
     std::fclose(fp);
-    return fail(c, TVLBM_EIO, "checkpoint does not match this context");
+    return fail(c, TVLBM_EIO, "short header");
+  }
+  if (const char* what = header_mismatch(h, make_header(c->d, c->rows ? c->dyh.data() : nullptr, 0))) {
+    std::fclose(fp);
+    return fail(c, TVLBM_EIO, std::string("checkpoint does not match this context: ") + what);
   }
   const size_t bytes = (size_t)c->hl.q * c->plane * esize(c);
   std::vector<char> host(bytes);

@@ -159,6 +159,8 @@ def lib():
                                 _dp, _dp, _dp, _dp],
         "tvlbm_save": [_vp, ctypes.c_char_p],
         "tvlbm_load": [_vp, ctypes.c_char_p],
+        "tvlbm_ckpt_header": [ctypes.POINTER(tvlbm_desc), ctypes.c_int64, _vp, ctypes.c_int64],
+        "tvlbm_ckpt_check": [_vp, ctypes.c_int64, ctypes.POINTER(tvlbm_desc), _i64p],
         "tvlbm_num_variants": [],
         "tvlbm_stream_copy": [_vp, _vp, ctypes.c_int64, _vp],
         "tvlbm_set_variant": [_vp, ctypes.c_int32],
@@ -323,6 +325,29 @@ def tvlbm_save(ctx, path: str):
 
 def tvlbm_load(ctx, path: str):
     _check(lib().tvlbm_load(ctx, path.encode()), ctx)
+
+
+TVLBM_CKPT_HEADER_BYTES = 128
+
+
+def tvlbm_ckpt_header(desc: "tvlbm_desc", step: int) -> bytes:
+    """Host only: the checkpoint header tvlbm_save writes for a context
+    built from desc at `step`."""
+    buf = ctypes.create_string_buffer(TVLBM_CKPT_HEADER_BYTES)
+    _check(lib().tvlbm_ckpt_header(ctypes.byref(desc), int(step), buf, TVLBM_CKPT_HEADER_BYTES))
+    return buf.raw
+
+
+def tvlbm_ckpt_check(header: bytes, desc: "tvlbm_desc"):
+    """Host only: the stored step count if tvlbm_load would accept a file
+    with this header for a context built from desc, else None."""
+    step = ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(bytes(header), len(header))
+    rc = lib().tvlbm_ckpt_check(buf, len(header), ctypes.byref(desc), ctypes.byref(step))
+    if rc == TVLBM_EIO:
+        return None
+    _check(rc)
+    return int(step.value)
 
 
 def tvlbm_set_variant(ctx, v: int):
