@@ -496,9 +496,42 @@ __device__ __forceinline__ int wrap_row(int j, int ny) {
   return j < 0 ? j + ny : j;
 }
 
+// Rows handed between the wavefronts of a workgroup (k_march2): the
+// x-pulled g^{k+1} of a first-step row, for the N * (N / 2) populations of
+// one y-sign, one value per lane.  Slot [0][w] holds what wave w hands over
+// at the start of its sweep, [1][w] at the end.
+template <typename R, int N>
+struct XchRows {
+  static constexpr int NL = N * (N / 2);
+  R v[2][4][NL][64];
+};
+
+// index of population (a, b), sign(x_b) = sg != 0, among those of its sign
+template <int N>
+__host__ __device__ constexpr int sign_index(int a, int b) {
+  return a * (N / 2) + (node_sign<N>(b) > 0 ? b - (N - N / 2) : b);
+}
+
+// One wave's segment [j0, j1) of the two-step march, direction DIR.
+// Exchanges with the neighbouring segments of the workgroup (same strip):
+//  * start (xs >= 0): the row behind the first output row is the first
+//    output row of segment xs, which marches the other way from the same
+//    boundary; each computes only its own and hands the other the x-pulled
+//    values of the populations that other treats as lead (its y2);
+//  * end (xe >= 0): the row past the last output row is the last output row
+//    of segment xe, which arrives there at the same time from the other
+//    side; each hands the other the values of the populations that other
+//    treats as trail (its x in the last second step).
+// Both hand-overs happen at fixed iterations (t = 1 and t = rows, barriers
+// for the whole workgroup), so every wave runs the same trip count; a wave
+// without a segment (live = false) takes part in the barriers only.  The
+// values are those the partner would compute itself (the first step of a
+// row does not depend on the direction of the march), so the results are
+// unchanged; each exchange saves one first-step row.
 template <typename R, int N, int ORD, bool COMP, int DIR>
 __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im, int ip,
-                                           bool active, int j0, int j1) {
+                                           bool active, bool live, int j0, int j1, int wave,
+                                           int xs, int xe, XchRows<R, N>& X, int lane) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
   const Inst<R>& P = A.inst;
@@ -510,12 +543,14 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
   const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
   const int nout = j1 - j0;
   const int jf = DIR > 0 ? j0 : j1 - 1;  // first output row
+  const int t0 = xs >= 0 ? 1 : 0;        // first first-step iteration
+  const int nt = A.rows + 2;             // same for every wave of the workgroup
 
-  // first-step rows r_t = jf + (t - 1) DIR, t = 0 .. nout + 1; before r_0,
-  // lead populations need X^k of the row behind it, trail ones of r_0 itself
+  // first-step rows r_t = jf + (t - 1) DIR; before r_{t0}, lead populations
+  // need X^k of the row behind it, trail ones of r_{t0} itself
   R hp[Q];
-  {
-    const int r0 = wrap_row(jf - DIR, ny);
+  if (live) {
+    const int r0 = wrap_row(jf + (t0 - 1) * DIR, ny);
     const RowOff ob = row_off((uint32_t)wrap_row(r0 - DIR, ny) * ld, ic, im, ip);
     const RowOff of = row_off((uint32_t)r0 * ld, ic, im, ip);
 #pragma unroll
@@ -537,50 +572,88 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
   R y1[Q], y2[Q];  // x-pulled g^{k+1} of the previous row and the one before
 #pragma unroll
   for (int l = 0; l < Q; ++l) y1[l] = y2[l] = R(0);
-  for (int t = 0; t < nout + 2; ++t) {
+  for (int t = 0; t < nt; ++t) {
     const int r = wrap_row(jf + (t - 1) * DIR, ny);
-    const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
-    const RowOff on = row_off((uint32_t)wrap_row(r + DIR, ny) * ld, ic, im, ip);
-    R d[Q];
+    R x[Q];
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
+    for (int l = 0; l < Q; ++l) x[l] = R(0);
+    if (live && t >= t0 && t <= nout + 1 && !(xe >= 0 && t == nout + 1)) {
+      const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
+      const RowOff on = row_off((uint32_t)wrap_row(r + DIR, ny) * ld, ic, im, ip);
+      R d[Q];
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        const int l = a * N + b;
-        const int sg = node_sign<N>(b);
-        const uint32_t pl = (uint32_t)(l * plane);
-        if (sg == DIR) {  // lead
-          const R hn = xpull<R, N>(L, s, pl, a, oj);
-          d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
-          hp[l] = hn;
-        } else if (sg == -DIR) {  // trail
-          const R hn = xpull<R, N>(L, s, pl, a, on);
-          d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
-          hp[l] = hn;
-        } else {
-          d[l] = xpull<R, N>(L, s, pl, a, oj);
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          const int sg = node_sign<N>(b);
+          const uint32_t pl = (uint32_t)(l * plane);
+          if (sg == DIR) {  // lead
+            const R hn = xpull<R, N>(L, s, pl, a, oj);
+            d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
+            hp[l] = hn;
+          } else if (sg == -DIR) {  // trail
+            const R hn = xpull<R, N>(L, s, pl, a, on);
+            d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
+            hp[l] = hn;
+          } else {
+            d[l] = xpull<R, N>(L, s, pl, a, oj);
+          }
+        }
+      }
+      R g[Q];
+      collide_regs<R, N, ORD, COMP>(L, P, d, g);
+      // x part of the second remap, upstream column from the neighbouring lane
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const int sa = node_sign<N>(a);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          if (sa > 0)
+            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
+          else if (sa < 0)
+            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
+          else
+            x[l] = g[l];
         }
       }
     }
-    R g[Q];
-    collide_regs<R, N, ORD, COMP>(L, P, d, g);
-    // x part of the second remap, upstream column from the neighbouring lane
-    R x[Q];
+    if (t == 1) {  // start hand-over: my first output row, the partner's lead
+      if (xs >= 0) {
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      const int sa = node_sign<N>(a);
+        for (int a = 0; a < N; ++a)
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        const int l = a * N + b;
-        if (sa > 0)
-          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
-        else if (sa < 0)
-          x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
-        else
-          x[l] = g[l];
+          for (int b = 0; b < N; ++b)
+            if (node_sign<N>(b) == -DIR) X.v[0][wave][sign_index<N>(a, b)][lane] = x[a * N + b];
+      }
+      __syncthreads();
+      if (xs >= 0) {  // the row behind my first output row, as if from t = 0
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b)
+            if (node_sign<N>(b) == DIR) y1[a * N + b] = X.v[0][xs][sign_index<N>(a, b)][lane];
       }
     }
-    if (t >= 2) {  // second step on output row m = r - DIR
+    if (t == A.rows) {  // end hand-over: my last output row, the partner's trail
+      if (xe >= 0) {
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b)
+            if (node_sign<N>(b) == DIR) X.v[1][wave][sign_index<N>(a, b)][lane] = x[a * N + b];
+      }
+      __syncthreads();
+    }
+    if (xe >= 0 && t == nout + 1) {  // the row past my last output row
+#pragma unroll
+      for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+          if (node_sign<N>(b) == -DIR) x[a * N + b] = X.v[1][xe][sign_index<N>(a, b)][lane];
+    }
+    if (live && t >= 2 && t <= nout + 1) {  // second step on output row m = r - DIR
       const uint32_t om = (uint32_t)wrap_row(r - DIR, ny) * ld + (uint32_t)ic;
       R e[Q];
 #pragma unroll
@@ -616,34 +689,46 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
   }
 }
 
-// One workgroup = 4 wavefronts = 4 consecutive row segments of one strip.
-// At least two wavefronts per SIMD: the D2Q36 form would otherwise take a
-// few registers past half the file and run one wavefront per SIMD, with no
-// other to hide its load latency; the few values spilled under the bound
-// cost less than that (the smaller lattices fit anyway).
+// One workgroup = 4 wavefronts = 4 consecutive row segments of one strip,
+// marching in alternating directions (even segments up), so that waves 1
+// and 2 start from a common boundary and waves 0, 1 and 2, 3 end at one;
+// those hand the boundary rows over (march2_dir) when both segments are
+// whole.  At least two wavefronts per SIMD: the D2Q36 form would otherwise
+// take a few registers past half the file and run one wavefront per SIMD,
+// with no other to hide its load latency; the few values spilled under the
+// bound cost less than that (the smaller lattices fit anyway).
 template <typename R, int N, int ORD, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march2(const MarchArgs<R> A) {
+  __shared__ XchRows<R, N> X;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nb = gridDim.x;  // multiple of 8
   const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-  if (t >= A.n_tiles) return;
-  const int nx = A.inst.nx, ny = A.inst.ny;
+  if (t >= A.n_tiles) return;  // whole workgroup
+  const int nx = A.inst.nx, ny = A.inst.ny, rows = A.rows;
   const int tx = t % A.tiles_x, ty = t / A.tiles_x;
-  const int group = ty * 4 + wave;
-  const int j0 = group * A.rows;
-  if (j0 >= ny) return;  // wave-uniform
-  const int j1 = min(j0 + A.rows, ny);
+  const int g0 = ty * 4;  // first segment of the workgroup
+  const int group = g0 + wave;
+  const int j0 = group * rows;
+  const bool live = j0 < ny;  // wave-uniform; a wave without rows still meets the barriers
+  const int j1 = min(j0 + rows, ny);
+  // segment w of this workgroup is whole (rows rows, all inside the grid)
+  auto whole = [&](int w) { return (g0 + w + 1) * rows <= ny; };
+  int xs = -1, xe = -1;
+  if (wave == 1 && whole(1) && (g0 + 2) * rows < ny) xs = 2;
+  if (wave == 2 && whole(1) && (g0 + 2) * rows < ny) xs = 1;
+  if ((wave == 0 || wave == 1) && whole(0) && whole(1)) xe = wave ^ 1;
+  if ((wave == 2 || wave == 3) && whole(2) && whole(3)) xe = wave ^ 1;
   const int col = tx * STRIP2 - 1 + lane;  // lanes 0 and 63 are halo
-  const bool active = lane >= 1 && lane <= STRIP2 && col < nx;
+  const bool active = live && lane >= 1 && lane <= STRIP2 && col < nx;
   int ic = col % nx;
   ic = ic < 0 ? ic + nx : ic;
   const int im = ic == 0 ? nx - 1 : ic - 1;
   const int ip = ic == nx - 1 ? 0 : ic + 1;
   if (group & 1)
-    march2_dir<R, N, ORD, COMP, -1>(A, ic, im, ip, active, j0, j1);
+    march2_dir<R, N, ORD, COMP, -1>(A, ic, im, ip, active, live, j0, j1, wave, xs, xe, X, lane);
   else
-    march2_dir<R, N, ORD, COMP, +1>(A, ic, im, ip, active, j0, j1);
+    march2_dir<R, N, ORD, COMP, +1>(A, ic, im, ip, active, live, j0, j1, wave, xs, xe, X, lane);
 }
 
 // ------------------------------------------- two steps per sweep, walls --
