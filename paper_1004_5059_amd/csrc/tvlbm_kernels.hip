@@ -548,7 +548,9 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
 
   // first-step rows r_t = jf + (t - 1) DIR; before r_{t0}, lead populations
   // need X^k of the row behind it, trail ones of r_{t0} itself
-  R hp[Q];
+  R hp[Q], hq[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) hp[l] = hq[l] = R(0);
   if (live) {
     const int r0 = wrap_row(jf + (t0 - 1) * DIR, ny);
     const RowOff ob = row_off((uint32_t)wrap_row(r0 - DIR, ny) * ld, ic, im, ip);
@@ -569,14 +571,26 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
     }
   }
 
-  R y1[Q], y2[Q];  // x-pulled g^{k+1} of the previous row and the one before
-#pragma unroll
-  for (int l = 0; l < Q; ++l) y1[l] = y2[l] = R(0);
-  for (int t = 0; t < nt; ++t) {
+  // One iteration t: first step on row r_t into x (xc, which on entry
+  // still holds x of t - 2, the y2 of the second step), then the second
+  // step on output row r_t - DIR from y1 = xp (x of t - 1), y2 and x.  The
+  // sweep runs two iterations per trip with the buffers swapped, so rows
+  // change roles without register moves; the lead part of the second step
+  // (which needs y2) is formed before x overwrites it.  hi / ho: X^k of the
+  // row behind, carried in, and carried out.
+  auto iter = [&](const int t, R (&hi)[Q], R (&ho)[Q], R (&xp)[Q], R (&xc)[Q]) {
     const int r = wrap_row(jf + (t - 1) * DIR, ny);
-    R x[Q];
+    const bool second = live && t >= 2 && t <= nout + 1;
+    R el[Q];  // lead part of the second step
+    if (second) {
 #pragma unroll
-    for (int l = 0; l < Q; ++l) x[l] = R(0);
+      for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int l = a * N + b;
+          if (node_sign<N>(b) == DIR) el[l] = fmaR(L.qm[b], xp[l], L.p[b] * xc[l]);
+        }
+    }
     if (live && t >= t0 && t <= nout + 1 && !(xe >= 0 && t == nout + 1)) {
       const RowOff oj = row_off((uint32_t)r * ld, ic, im, ip);
       const RowOff on = row_off((uint32_t)wrap_row(r + DIR, ny) * ld, ic, im, ip);
@@ -589,13 +603,11 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
           const int sg = node_sign<N>(b);
           const uint32_t pl = (uint32_t)(l * plane);
           if (sg == DIR) {  // lead
-            const R hn = xpull<R, N>(L, s, pl, a, oj);
-            d[l] = fmaR(L.qm[b], hn, L.p[b] * hp[l]);
-            hp[l] = hn;
+            ho[l] = xpull<R, N>(L, s, pl, a, oj);
+            d[l] = fmaR(L.qm[b], ho[l], L.p[b] * hi[l]);
           } else if (sg == -DIR) {  // trail
-            const R hn = xpull<R, N>(L, s, pl, a, on);
-            d[l] = fmaR(L.qm[b], hp[l], L.p[b] * hn);
-            hp[l] = hn;
+            ho[l] = xpull<R, N>(L, s, pl, a, on);
+            d[l] = fmaR(L.qm[b], hi[l], L.p[b] * ho[l]);
           } else {
             d[l] = xpull<R, N>(L, s, pl, a, oj);
           }
@@ -611,12 +623,21 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
         for (int b = 0; b < N; ++b) {
           const int l = a * N + b;
           if (sa > 0)
-            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
+            xc[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_PREV>(g[l]));
           else if (sa < 0)
-            x[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
+            xc[l] = fmaR(L.qm[a], g[l], L.p[a] * lane_from<DPP_NEXT>(g[l]));
           else
-            x[l] = g[l];
+            xc[l] = g[l];
         }
+      }
+    } else {
+      // no first step (t = 0 before a start hand-over, the row taken from
+      // the end partner, rows past the segment, no segment): the carried
+      // row passes on; of x only the parts the hand-overs write are used
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        ho[l] = hi[l];
+        xc[l] = R(0);
       }
     }
     if (t == 1) {  // start hand-over: my first output row, the partner's lead
@@ -625,7 +646,7 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
         for (int a = 0; a < N; ++a)
 #pragma unroll
           for (int b = 0; b < N; ++b)
-            if (node_sign<N>(b) == -DIR) X.v[0][wave][sign_index<N>(a, b)][lane] = x[a * N + b];
+            if (node_sign<N>(b) == -DIR) X.v[0][wave][sign_index<N>(a, b)][lane] = xc[a * N + b];
       }
       __syncthreads();
       if (xs >= 0) {  // the row behind my first output row, as if from t = 0
@@ -633,7 +654,7 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
         for (int a = 0; a < N; ++a)
 #pragma unroll
           for (int b = 0; b < N; ++b)
-            if (node_sign<N>(b) == DIR) y1[a * N + b] = X.v[0][xs][sign_index<N>(a, b)][lane];
+            if (node_sign<N>(b) == DIR) xp[a * N + b] = X.v[0][xs][sign_index<N>(a, b)][lane];
       }
     }
     if (t == A.rows) {  // end hand-over: my last output row, the partner's trail
@@ -642,7 +663,7 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
         for (int a = 0; a < N; ++a)
 #pragma unroll
           for (int b = 0; b < N; ++b)
-            if (node_sign<N>(b) == DIR) X.v[1][wave][sign_index<N>(a, b)][lane] = x[a * N + b];
+            if (node_sign<N>(b) == DIR) X.v[1][wave][sign_index<N>(a, b)][lane] = xc[a * N + b];
       }
       __syncthreads();
     }
@@ -651,9 +672,9 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
       for (int a = 0; a < N; ++a)
 #pragma unroll
         for (int b = 0; b < N; ++b)
-          if (node_sign<N>(b) == -DIR) x[a * N + b] = X.v[1][xe][sign_index<N>(a, b)][lane];
+          if (node_sign<N>(b) == -DIR) xc[a * N + b] = X.v[1][xe][sign_index<N>(a, b)][lane];
     }
-    if (live && t >= 2 && t <= nout + 1) {  // second step on output row m = r - DIR
+    if (second) {  // second step on output row m = r - DIR
       const uint32_t om = (uint32_t)wrap_row(r - DIR, ny) * ld + (uint32_t)ic;
       R e[Q];
 #pragma unroll
@@ -663,11 +684,11 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
           const int l = a * N + b;
           const int sg = node_sign<N>(b);
           if (sg == DIR)
-            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * y2[l]);
+            e[l] = el[l];
           else if (sg == -DIR)
-            e[l] = fmaR(L.qm[b], y1[l], L.p[b] * x[l]);
+            e[l] = fmaR(L.qm[b], xp[l], L.p[b] * xc[l]);
           else
-            e[l] = y1[l];
+            e[l] = xp[l];
         }
       }
       R g2[Q];
@@ -677,15 +698,16 @@ __device__ __forceinline__ void march2_dir(const MarchArgs<R>& A, int ic, int im
         for (int l = 0; l < Q; ++l) bst(dst, om, (uint32_t)(l * plane), g2[l]);
       }
     }
+  };
+
+  // Pairs of iterations; a last iteration past nt does nothing (the
+  // barriers sit at t = 1 and t = rows, below nt).
+  R xa[Q], xb[Q];
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        const int l = a * N + b;
-        if (node_sign<N>(b) == DIR) y2[l] = y1[l];
-        y1[l] = x[l];
-      }
-    }
+  for (int l = 0; l < Q; ++l) xa[l] = xb[l] = R(0);
+  for (int t = 0; t < nt; t += 2) {
+    iter(t, hp, hq, xb, xa);
+    iter(t + 1, hq, hp, xa, xb);
   }
 }
 
@@ -1388,10 +1410,22 @@ __global__ __launch_bounds__(256) void k_mass_fix(R* __restrict__ g, const Inst<
   const int64_t n = (int64_t)P.nx * P.ny;  // < 2^31 (a plane is 32-bit addressed)
   const int k0 = (int)(n * sl / RESID_SLICES), k1 = (int)(n * (sl + 1) / RESID_SLICES);
   const uint32_t nx = (uint32_t)P.nx;
+  const int64_t pl = P.plane;
   for (int c = k0 + (int)threadIdx.x; c < k1; c += 256) {
     const uint32_t j = (uint32_t)c / nx, i = (uint32_t)c - j * nx;
     R* p = g + P.off + (int64_t)j * P.ld + i;
-    for (int l = 0; l < q; ++l, p += P.plane) *p = fmaR(L.w[l], delta, *p);
+    // eight loads ahead of their stores: the compiler cannot tell the
+    // populations' addresses apart, and would otherwise wait out one load
+    // per population
+    int l = 0;
+    for (; l + 8 <= q; l += 8) {
+      R v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(l + u) * pl];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[(l + u) * pl] = fmaR(L.w[l + u], delta, v[u]);
+    }
+    for (; l < q; ++l) p[l * pl] = fmaR(L.w[l], delta, p[l * pl]);
   }
 }
 
