@@ -144,7 +144,7 @@ def run_fv(n: int, size: int, steps: int, warmup: int, dtype: str = "f32", walls
 
 
 def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k: int = 100,
-                solve: bool = True, load_steps: int = 500):
+                solve: bool = True, load_steps: int = 500, two_rows: int = 0):
     """Batched steady solves of the thermal-Couette sampler (seed 2026) in one
     persistent, graph-captured run, against plain single-instance solves.
 
@@ -156,7 +156,9 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
     per step of its size (residual checks included).
 
     Before the solve, load_steps steps with every instance active give the
-    batched kernel's full-load throughput; solve=False stops there."""
+    batched kernel's full-load throughput; solve=False stops there.
+    two_rows > 0: a fixed tuning (two-step segments of two_rows rows)
+    instead of the autotuner's, for counter runs that must repeat exactly."""
     import numpy as np
     import torch
 
@@ -166,7 +168,11 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
 
     insts = inputs.couette_instances(n_inst, seed=2026)
     t0 = time.perf_counter()
-    tune = autotune_batch(insts)
+    if two_rows > 0:
+        tune = {"tuning": dict(prefetch=0, tail_active=64, tail_width=64, tail_rows=6, two_step=1,
+                               two_rows=two_rows), "shapes": {}}
+    else:
+        tune = autotune_batch(insts)
     t_tune = time.perf_counter() - t0
     b = BatchSolver(insts, dtype="f32")
     apply_batch_tuning(b, tune)
@@ -417,10 +423,12 @@ def counters_from_profile(steps_per_launch: int, variant: int):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if (d.get("kernel_hash") != _kernel_hash() or d.get("steps_per_launch", 1) != steps_per_launch
-            or d.get("variant") != variant):
+    if d.get("kernel_hash") != _kernel_hash():
         return None
-    return d
+    v = d.get("variants", {}).get(str(variant))
+    if v is None or v.get("steps_per_launch") != steps_per_launch:
+        return None
+    return v
 
 
 def main():
@@ -447,6 +455,15 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--fv-only", action="store_true", help="run only the finite-volume legs")
     ap.add_argument("--fv-size", type=int, default=1024, help="mesh size of the finite-volume legs")
+    ap.add_argument("--profile-variants", default="",
+                    help="comma-separated D2Q16 launch variants: run only the D2Q16 leg once per "
+                         "variant (steps/warmup as given) and one 256 MiB stream copy, for counter "
+                         "runs under rocprofv3, then exit")
+    ap.add_argument("--profile-variants36", default="",
+                    help="with --profile-variants: D2Q36 launch variants to run the same way")
+    ap.add_argument("--batched-two-rows", type=int, default=0,
+                    help="batched leg: fixed two-step segment rows instead of autotuning "
+                         "(for counter runs)")
     ap.add_argument("--batched-load-only", action="store_true",
                     help="batched leg: full-load steps only, no steady solves")
     args = ap.parse_args()
@@ -480,6 +497,22 @@ def main():
     if args.fv_only:
         print(json.dumps({"fv": fv_legs()}), flush=True)
         return
+    if args.profile_variants:
+        # each variant's k_march2 launches have their own grid size, which
+        # tells them apart in a counter run; the copy calibrates the counters
+        res = {}
+        for v in (int(x) for x in args.profile_variants.split(",")):
+            r = leg(f"D2Q16 variant {v}", run_lattice, 4, args.size, args.steps, args.warmup, v)
+            res[str(v)] = {"mlups": round(r["mlups"], 1), "launch_us": round(r["launch_ms"] * 1e3, 3),
+                           "steps_per_launch": r["steps_per_launch"]}
+        for v in (int(x) for x in args.profile_variants36.split(",") if x):
+            r = leg(f"D2Q36 variant {v}", run_lattice, 6, args.size, args.steps, args.warmup, v)
+            res[f"d2q36_{v}"] = {"mlups": round(r["mlups"], 1),
+                                 "launch_us": round(r["launch_ms"] * 1e3, 3),
+                                 "steps_per_launch": r["steps_per_launch"]}
+        res["copy"] = leg("stream copy", copy_ceiling, 256, 3)
+        print(json.dumps({"profile_variants": res}), flush=True)
+        return
     # The headline leg runs first: once other solvers have allocated and freed
     # device memory, the same step on new buffers runs 3-5 % slower (measured
     # 25.3-25.6 us against 24.5 us at 1024^2 D2Q16, even after emptying
@@ -497,7 +530,7 @@ def main():
     c0 = None if args.no_f64 else leg("C0 64x64 FP64", run_c0)
     cp = None if args.no_copy else leg("copy ceiling", copy_ceiling)
     bat = None if args.no_batched else leg("batched", run_batched, 256, 2, 1e-8, 100,
-                                           not args.batched_load_only)
+                                           not args.batched_load_only, 500, args.batched_two_rows)
     c2 = None if args.no_c2 else leg("C2 bounded flow", run_c2)
     c4 = None if args.no_c4 else leg("C4 warm start", run_c4)
     cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)

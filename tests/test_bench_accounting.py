@@ -11,10 +11,11 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def _write(tmp_path, **kw):
-    d = {"kernel_hash": bench._kernel_hash(), "steps_per_launch": 2, "variant": 22,
-         "hbm_bytes_per_launch": 123456789, "sq_insts_valu_per_dispatch": 1000}
-    d.update(kw)
+def _write(tmp_path, kernel_hash=None, **kw):
+    v = {"steps_per_launch": 2, "hbm_bytes_per_launch": 123456789,
+         "sq_insts_valu_per_dispatch": 1000}
+    v.update(kw)
+    d = {"kernel_hash": kernel_hash or bench._kernel_hash(), "variants": {"22": v}}
     (tmp_path / "profiles").mkdir(exist_ok=True)
     (tmp_path / "profiles" / "fused_step_d2q16_1024_counters.json").write_text(json.dumps(d))
 
@@ -40,15 +41,24 @@ def test_counters_without_a_counter_file(tmp_path, monkeypatch):
 
 def test_committed_counter_file_is_complete():
     d = json.load(open(os.path.join(ROOT, "profiles", "fused_step_d2q16_1024_counters.json")))
-    for k in ("kernel", "kernel_hash", "variant", "steps_per_launch", "fetch_size_kib_per_dispatch",
-              "write_size_kib_per_dispatch", "hbm_bytes_per_launch",
-              "algorithmic_bytes_per_launch", "commands"):
+    for k in ("kernel", "kernel_hash", "calibration", "variants", "commands"):
         assert k in d, k
-    # reads = 2.0 x FETCH_SIZE, writes = 1.0 x WRITE_SIZE, KiB per dispatch
-    want = (d["fetch_calibration"] * d["fetch_size_kib_per_dispatch"]
-            + d["write_calibration"] * d["write_size_kib_per_dispatch"]) * 1024
-    assert abs(d["hbm_bytes_per_launch"] - want) <= 1
-    assert d["algorithmic_bytes_per_launch"] == 2 * 16 * 4 * 1024 * 1024 * d["steps_per_launch"]
+    cal = d["calibration"]
+    # the copy kernel of known size fixes bytes per counted KiB
+    assert abs(cal["fetch_factor"] * cal["fetch_size_kib_per_dispatch"] * 1024
+               - cal["bytes_read_per_dispatch"]) <= 1024
+    assert abs(cal["write_factor"] * cal["write_size_kib_per_dispatch"] * 1024
+               - cal["bytes_written_per_dispatch"]) <= 1024
+    assert d["variants"]
+    for name, v in d["variants"].items():
+        for k in ("steps_per_launch", "grid_size", "fetch_size_kib_per_dispatch",
+                  "write_size_kib_per_dispatch", "hbm_bytes_per_launch",
+                  "algorithmic_bytes_per_launch", "sq_insts_valu_per_dispatch"):
+            assert k in v, (name, k)
+        want = (cal["fetch_factor"] * v["fetch_size_kib_per_dispatch"]
+                + cal["write_factor"] * v["write_size_kib_per_dispatch"]) * 1024
+        assert abs(v["hbm_bytes_per_launch"] - want) <= 1
+        assert v["algorithmic_bytes_per_launch"] == 2 * 16 * 4 * 1024 * 1024 * v["steps_per_launch"]
     assert all(c.startswith("rocprofv3 --pmc ") for c in d["commands"])
 
 
