@@ -53,11 +53,11 @@ def run_lattice(n: int, size: int, steps: int, warmup: int, variant: int, dtype:
     ev[0].record(s.stream)
     s.step(steps)
     ev[1].record(s.stream)
-    # With two steps per launch, tvlbm_step makes (steps-1)//2 two-step
-    # launches and ends with one or two single steps (state semantics); time
-    # single-step launches on their own on the same stream, so that the
-    # two-step kernel's average launch duration can be separated.
-    n2 = (steps - 1) // 2 if k == 2 else 0
+    # With two steps per launch, tvlbm_step makes steps//2 two-step launches
+    # and, for an odd count, one single step; time single-step launches on
+    # their own on the same stream, so that the two-step kernel's average
+    # launch duration can be separated.
+    n2 = steps // 2 if k == 2 else 0
     n1 = steps - 2 * n2
     reps1 = 20
     ev[2].record(s.stream)

@@ -98,7 +98,8 @@ int tvlbm_set_fields(tvlbm_ctx *ctx, const void *rho, const void *ux,
 /* f^0 = f (device [q][ny][nx], absolute populations), step counter 0. */
 int tvlbm_set_populations(tvlbm_ctx *ctx, const void *f);
 
-/* Advance nsteps >= 0 steps (asynchronous). */
+/* Advance nsteps >= 0 steps (asynchronous); see tvlbm_set_variant for the
+ * launches a two-step variant makes. */
 int tvlbm_step(tvlbm_ctx *ctx, int32_t nsteps);
 
 /* f^k (absolute, pre-collision) into device [q][ny][nx]; asynchronous. */
@@ -132,9 +133,11 @@ int tvlbm_moments(tvlbm_ctx *ctx, void *rho, void *ux, void *uy, void *T,
  * 4,194,304 with non-uniform rows) are rejected with EINVAL before anything
  * is enqueued.  Calls that overlap on one GPU (several contexts or streams
  * at once) race on that array.  EINVAL also if the current device is not the
- * context's, or the populations are not set.  A captured call reads the
- * buffer that holds the state when it is captured (the two buffers swap at
- * every launch of tvlbm_step): replay it when the context is back in that
+ * context's, or the populations are not set.  If the last launch was a
+ * two-step one, the call first enqueues the step and the copy kernel that
+ * form g^{k-1} (see tvlbm_set_variant).  A captured call reads the buffer
+ * that holds the state when it is captured (the two buffers swap at every
+ * launch of tvlbm_step): replay it when the context is back in that
  * buffer, e.g. in a graph that also holds the steps, advancing an even
  * number of launches. */
 int tvlbm_moments_static(tvlbm_ctx *ctx, void *fields, double *totals, int32_t *flag);
@@ -200,9 +203,14 @@ int tvlbm_ckpt_check(const void *header, int64_t bytes, const tvlbm_desc *desc, 
  * written once per two steps) on the grids that kernel covers (uniform
  * rows, periodic or with walls; FP32 with n_gh 3, 4 or 6, FP64 with n_gh 3
  * or 4); elsewhere they run variant 0.
- * tvlbm_step(ctx, n) with such a variant makes floor((n-1)/2) two-step
- * launches and one or two single steps, so that the state after the call
- * is the same as with single steps. */
+ * tvlbm_step(ctx, n) with such a variant makes floor(n/2) two-step
+ * launches and, for odd n, one single step.  After a two-step launch the
+ * library has not formed g^{k-1} (from which the populations, moments,
+ * residual and checkpoint of step k are taken); the next call that needs it
+ * forms it first, with one step into a third population buffer of the
+ * library and a copy kernel, bitwise what single steps would have left.
+ * Selecting such a variant allocates that buffer (q*ny*ld elements of the
+ * context's dtype; ENOMEM if it cannot), so no later call allocates. */
 int tvlbm_num_variants(void);
 int tvlbm_set_variant(tvlbm_ctx *ctx, int32_t variant);
 /* Steps the step kernel advances per launch with the current variant on

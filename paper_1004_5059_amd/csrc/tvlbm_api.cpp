@@ -77,7 +77,11 @@ struct tvlbm_ctx {
   int64_t ld = 0, plane = 0;
   hipStream_t st = nullptr;
   void* buf[2] = {nullptr, nullptr};
-  int cur = 0;          // buf[cur] holds g^k; buf[cur^1] holds g^{k-1} (or f^0)
+  int cur = 0;          // buf[cur] holds g^k; buf[cur^1] holds g^{k-1} (or f^0),
+                        // or g^{k-2} while `pending`
+  bool pending = false; // the last launch was a two-step one: g^{k-1} not formed yet
+  void* buf3 = nullptr; // library-owned population buffer for forming g^{k-1}
+                        // (allocated when a two-step variant is selected)
   int64_t step = 0;
   bool initialised = false;
   int variant = 0;
@@ -674,6 +678,7 @@ int tvlbm_destroy(tvlbm_ctx* c) {
   hipFree(c->d_rowflag);
   hipFree(c->d_mass);
   hipFree(c->d_area);
+  hipFree(c->buf3);
   delete c;
   return TVLBM_OK;
 }
@@ -700,6 +705,7 @@ static int set_common(tvlbm_ctx* c, const void* rho, const void* ux, const void*
   }
   c->cur = 0;
   c->step = 0;
+  c->pending = false;
   c->initialised = true;
   c->fld_valid = false;
   return TVLBM_OK;
@@ -719,23 +725,46 @@ int tvlbm_set_populations(tvlbm_ctx* c, const void* f) {
 int tvlbm_step(tvlbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, TVLBM_EINVAL, "nsteps");
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
-  if (two_ok(c)) {
-    // the last launch is a single step, so that the other buffer keeps
-    // g^{k-1}, from which the populations and moments of step k are formed
-    for (int32_t p = 0; p < (nsteps - 1) / 2; ++p) {
+  if (two_ok(c) && c->buf3) {
+    // two steps per launch; an odd count ends with a single step.  After a
+    // two-step launch the other buffer holds g^{k-2}: g^{k-1}, from which
+    // the populations and moments of step k are formed, is formed when one
+    // of those is asked for (settle)
+    for (int32_t p = 0; p < nsteps / 2; ++p) {
       int rc = march2(c, c->buf[c->cur], c->buf[c->cur ^ 1]);
       if (rc) return rc;
       c->cur ^= 1;
       c->step += 2;
+      c->pending = true;
     }
-    nsteps -= 2 * ((nsteps - 1) / 2);
+    nsteps -= 2 * (nsteps / 2);
   }
   for (int32_t s = 0; s < nsteps; ++s) {
     int rc = march(c, MODE_STEP, 0, c->buf[c->cur], c->buf[c->cur ^ 1], nullptr, false);
     if (rc) return rc;
     c->cur ^= 1;
     ++c->step;
+    c->pending = false;
   }
+  return TVLBM_OK;
+}
+
+// After two-step launches the other buffer holds g^{k-2}.  One step from it
+// into the library's third buffer forms g^{k-1} (bitwise what the two-step
+// launch formed on the way), which is copied into the other buffer; the
+// state is then as after single steps.  Allocates nothing: the third buffer
+// exists whenever a two-step launch could have run.
+static int settle(tvlbm_ctx* c) {
+  if (!c->pending) return TVLBM_OK;
+  if (!c->buf3) return fail(c, TVLBM_EINVAL, "internal: no buffer to form g^(k-1) in");
+  int rc = march(c, MODE_STEP, 0, c->buf[c->cur ^ 1], c->buf3, nullptr, false);
+  if (rc) return rc;
+  // a copy kernel, not a runtime copy: tvlbm_moments_static enqueues kernels
+  // only (the buffers are multiples of 256 bytes: ld is a multiple of 64)
+  const int64_t n16 = (int64_t)c->hl.q * c->plane * (int64_t)esize(c) / 16;
+  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 8192);
+  HIPCHK(c, launch_stream_copy(c->buf3, c->buf[c->cur ^ 1], n16, nblocks, c->st));
+  c->pending = false;
   return TVLBM_OK;
 }
 
@@ -743,6 +772,8 @@ int tvlbm_step(tvlbm_ctx* c, int32_t nsteps) {
 static int aux_from_state(tvlbm_ctx* c, int aux, void* dst, void* fields, bool totals,
                           unsigned long long* mass = nullptr) {
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
+  int rc = settle(c);
+  if (rc) return rc;
   if (c->step == 0) aux |= AUX_IDENTITY;
   Sink k = ctx_sink(c);
   k.mass = mass;
@@ -800,6 +831,8 @@ int tvlbm_moments_static(tvlbm_ctx* c, void* fields, double* totals, int32_t* fl
     return fail(c, TVLBM_EINVAL,
                 "grid too large for tvlbm_moments_static: " + std::to_string(g.nblocks) +
                     " partial blocks, the static scratch holds " + std::to_string(SCRATCH_BLOCKS));
+  int rc = settle(c);
+  if (rc) return rc;
   int32_t* fl = flag ? flag : (int32_t*)(base + SCRATCH_FLAG);
   HIPCHK(c, launch_fill_i32(fl, 1, 0, c->st));
   const Sink k{base, SCRATCH_BLOCKS, totals, fl, true};
@@ -921,6 +954,14 @@ int tvlbm_steps_per_launch(const tvlbm_ctx* c, int32_t* k) {
 int tvlbm_set_variant(tvlbm_ctx* c, int32_t v) {
   if (!c || v < 0 || v >= kNumVariants) return fail(c, TVLBM_EINVAL, "variant");
   c->variant = v;
+  if (two_ok(c) && !c->buf3) {
+    const size_t bytes = (size_t)c->hl.q * c->plane * esize(c);
+    if (hipMalloc(&c->buf3, bytes) != hipSuccess) {
+      c->buf3 = nullptr;
+      (void)hipGetLastError();
+      return fail(c, TVLBM_ENOMEM, "third population buffer for two-step launches");
+    }
+  }
   return TVLBM_OK;
 }
 
@@ -1006,6 +1047,7 @@ int tvlbm_ckpt_check(const void* header, int64_t bytes, const tvlbm_desc* desc, 
 int tvlbm_save(tvlbm_ctx* c, const char* path) {
   if (!c || !path) return TVLBM_EINVAL;
   if (!c->initialised) return fail(c, TVLBM_EINVAL, "populations not set");
+  if (int rc = settle(c)) return rc;  // the file holds g^k and g^{k-1}
   const CkptHeader h = make_header(c->d, c->rows ? c->dyh.data() : nullptr, c->step);
   const size_t bytes = (size_t)c->hl.q * c->plane * esize(c);
   std::vector<char> host(bytes);
@@ -1052,6 +1094,7 @@ int tvlbm_load(tvlbm_ctx* c, const char* path) {
   }
   std::fclose(fp);
   c->cur = 0;
+  c->pending = false;
   c->step = h.step;
   c->initialised = true;
   c->fld_valid = false;

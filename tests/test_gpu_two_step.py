@@ -298,3 +298,58 @@ def test_walled_two_step_against_the_oracle(n, dtype, tol):
     assert rel_inf(s.populations().cpu().numpy(), fr) <= tol
     assert abs(t1[0] - t0[0]) / t0[0] <= (1e-13 if dtype == "f64" else 1e-6)
     s.close()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_state_after_even_two_step_runs(tmp_path, walls):
+    """An even step count on a two-step variant ends with a two-step launch,
+    and g^{k-1} (from which f^k, the fields and the totals come) is formed
+    when first asked for.  Every way of observing the state right after such
+    runs -- moments, the allocation-free moments, populations, the residual,
+    a checkpoint -- and stepping on afterwards must match single steps
+    bitwise."""
+    from paper_1004_5059_amd import tvlbm as T
+
+    nx, ny = 70, 23
+    kw = WALLS if walls else {}
+    fields, noise = c0_inputs(nx, ny, q=16, seed=31)
+    ref = Solver(nx, ny, n_gh=4, dtype="f32", tau=0.7, **kw)
+    ref.set_fields(*fields, noise)
+    s = Solver(nx, ny, n_gh=4, dtype="f32", tau=0.7, **kw)
+    s.set_variant(22)
+    assert s.steps_per_launch() == 2
+    s.set_fields(*fields, noise)
+    for k in (2, 4, 6):  # cumulative 2, 6, 12: all two-step launches
+        ref.step(k)
+        s.step(k)
+        fld = torch.empty((4, ny, nx), dtype=torch.float32, device="cuda:0")
+        tot = torch.empty(4, dtype=torch.float64, device="cuda:0")
+        T.tvlbm_moments_static(s.ctx, fld, tot, None)  # the first observer forms g^{k-1}
+        torch.cuda.synchronize()
+        F, t_ref = ref.moments()
+        assert np.array_equal(fld.cpu().numpy(), F.cpu().numpy()), k
+        assert np.array_equal(tot.cpu().numpy(), np.asarray(t_ref)), k
+        for x, y in zip(_state(s), _state(ref)):
+            assert np.array_equal(x, y), k
+    # the residual of a solve over even chunks, and a checkpoint taken right
+    # after a two-step launch, continued on the one-step variant
+    s.residual(), ref.residual()  # snapshots
+    ref.step(8)
+    s.step(8)
+    r_s, r_ref = s.residual(), ref.residual()
+    assert np.isfinite(r_s) and r_s == r_ref
+    ref.step(4)
+    s.step(4)
+    p = str(tmp_path / "ck.bin")
+    T.tvlbm_save(s.ctx, p)
+    t = Solver(nx, ny, n_gh=4, dtype="f32", tau=0.7, **kw)
+    T.tvlbm_load(t.ctx, p)
+    assert t.step_count == ref.step_count
+    for x, y in zip(_state(t), _state(ref)):
+        assert np.array_equal(x, y)
+    t.step(5)
+    ref.step(5)
+    for x, y in zip(_state(t), _state(ref)):
+        assert np.array_equal(x, y)
+    for x in (s, t, ref):
+        x.close()
