@@ -40,7 +40,11 @@ const Variant kVariants[] = {{64, 4, 0}, {64, 2, 1}, {64, 8, 1}, {64, 16, 1}, {6
                              {64, 4, 0, 1}, {64, 8, 0, 1}, {64, 2, 0, 1}, {64, 16, 0, 1},
                              {32, 8, 0, 1},
                              {64, 3, 0, 0, 1}, {64, 4, 0, 0, 1}, {64, 5, 0, 0, 1},
-                             {64, 6, 0, 0, 1}, {64, 8, 0, 0, 1}};
+                             {64, 6, 0, 0, 1}, {64, 8, 0, 0, 1},
+                             // longer two-step segments: fewer wavefronts, so that a
+                             // lattice at two waves per SIMD (D2Q36) fills one round
+                             {64, 7, 0, 0, 1}, {64, 9, 0, 0, 1}, {64, 10, 0, 0, 1},
+                             {64, 12, 0, 0, 1}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

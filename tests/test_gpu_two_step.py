@@ -17,8 +17,9 @@ from gpu_common import c0_inputs, make_pair, rel_inf  # noqa: E402
 from paper_1004_5059_amd import inputs, tvlbm  # noqa: E402
 from paper_1004_5059_amd.tvlbm import Solver  # noqa: E402
 
-# the variant table's two-step entries (output rows per segment 3, 4, 5, 6, 8)
-TWO = [19, 20, 21, 22, 23]
+# the variant table's two-step entries (output rows per segment 3, 4, 5, 6,
+# 8, 7, 9, 10, 12)
+TWO = [19, 20, 21, 22, 23, 24, 25, 26, 27]
 
 
 def _solver(nx, ny, n, variant, dtype="f32", compensated=True, walls=False, tau=0.7):
@@ -34,7 +35,7 @@ def _state(s):
 
 
 def test_variant_table_has_the_two_step_entries():
-    assert tvlbm.tvlbm_num_variants() == 24
+    assert tvlbm.tvlbm_num_variants() == 28
     s = _solver(64, 16, 4, TWO[0])
     assert s.steps_per_launch() == 2
     s.set_variant(0)
