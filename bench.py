@@ -234,6 +234,7 @@ def run_batched(n_inst: int = 256, plain_per_size: int = 2, tol: float = 1e-8, k
         "plain_wall_s_est": round(t_plain, 3), "plain_solves_per_s": round(n_inst / t_plain, 3),
         "speedup": round(t_plain / t_batch, 2),
         "aggregate_mlups": round(float(np.sum(cells * steps)) / t_batch / 1e6, 1),
+        "cell_updates": float(np.sum(cells * steps)),
         "steps_max": int(np.max(steps)), "steps_mean": float(np.mean(steps)),
         "plain_sample": f"{len(sample)} instances ({plain_per_size} per N_y) solved one by one; "
                         "whole-batch plain time = sum of steps x per-size time per step",
@@ -395,9 +396,15 @@ def run_c4(n_train: int = 4096, n_test: int = 256, epochs: int = 40, batch: int 
     return out
 
 
-def cpu_baseline(size: int, target_s: float = 15.0):
+def cpu_baseline(size: int, target_s: float = 15.0, c3_cell_updates: float = 0.0):
     """The FP64 oracle, as it stands, on this host's cores: a bounded sample
-    (a few steps of the same 1024^2 D2Q16 workload)."""
+    (a few steps of the same 1024^2 D2Q16 workload), the same on one core,
+    and the walled channels of the batched solve: one instance per N_y of
+    the sampler, 50 steps each, whose cell-update rate gives an estimate of
+    the oracle's time for the whole batch (c3_cell_updates: the batch's
+    total cell-updates to convergence, from the batched leg)."""
+    import numpy as np
+
     from oracle import oracle as orc
     from paper_1004_5059_amd import inputs
 
@@ -410,11 +417,40 @@ def cpu_baseline(size: int, target_s: float = 15.0):
     one = (time.perf_counter() - t) / 4
     steps = max(1, min(2000, int(target_s / max(one, 1e-3))))
     t = time.perf_counter()
-    g.run(f, steps)
+    f = g.run(f, steps)
     dt = time.perf_counter() - t
-    return {"value": size * size * steps / dt / 1e6, "unit": "MLUPS", "cores": orc.threads(),
-            "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the {size}x{size} D2Q16 workload"}
+    cores = orc.threads()
+    out = {"value": size * size * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{steps} FP64 oracle steps of the {size}x{size} D2Q16 workload"}
+    orc.set_threads(1)
+    try:
+        t = time.perf_counter()
+        g.run(f, 3)
+        out["one_core_mlups"] = round(size * size * 3 / (time.perf_counter() - t) / 1e6, 3)
+    finally:
+        orc.set_threads(cores)
+    # walled channels of the batched solve, one per N_y
+    insts = inputs.couette_instances(256, seed=2026)
+    pick = {}
+    for d in insts:
+        pick.setdefault(d["ny"], d)
+    cells, secs = 0, 0.0
+    for ny in sorted(pick):
+        d = pick[ny]
+        gw = orc.OracleGrid(lat, d["nx"], d["ny"], tau=d["tau"], walls=True,
+                            wall_lo=(0.0, d["T_bot"]), wall_hi=(d["u_top"], d["T_top"]))
+        fw = gw.run(gw.set_fields(*inputs.uniform_fields(d["nx"], d["ny"])), 1)
+        t = time.perf_counter()
+        gw.run(fw, 50)
+        secs += time.perf_counter() - t
+        cells += d["nx"] * d["ny"] * 50
+    rate = cells / secs
+    out["c3_subset"] = {"instances": len(pick), "steps_each": 50, "mlups": round(rate / 1e6, 2),
+                        "cores": cores}
+    if c3_cell_updates > 0:
+        out["c3_subset"]["oracle_batch_s_est"] = round(c3_cell_updates / rate, 1)
+    return out
 
 
 def counters_from_profile(steps_per_launch: int, variant: int):
@@ -537,7 +573,8 @@ def main():
                                            not args.batched_load_only, 500, args.batched_two_rows)
     c2 = None if args.no_c2 else leg("C2 bounded flow", run_c2)
     c4 = None if args.no_c4 else leg("C4 warm start", run_c4)
-    cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size)
+    cpu = None if args.no_cpu_baseline else leg("cpu baseline", cpu_baseline, args.size, 15.0,
+                                                (bat or {}).get("cell_updates", 0.0))
     achieved = r16["achieved_gbs"]
     prof = counters_from_profile(r16["steps_per_launch"], r16["variant"])
     traffic = None if prof is None else prof.get("hbm_bytes_per_launch")

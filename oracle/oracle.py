@@ -121,6 +121,7 @@ def lib():
         _lib.orc_residual.argtypes = [_dp, _dp, ctypes.c_long, ctypes.c_int]
         _lib.orc_residual.restype = ctypes.c_double
         _lib.orc_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
         FG = ctypes.POINTER(FVGrid)
         _lib.orc_fv_init.argtypes = [L, FG, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -386,3 +387,8 @@ def residual(q: np.ndarray, qprev: np.ndarray, K: int) -> float:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_threads(int(n))

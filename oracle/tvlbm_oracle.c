@@ -535,3 +535,12 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the parallel loops that follow (n >= 1); for timing only. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
