@@ -567,7 +567,7 @@ int tvlbm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream) {
     return TVLBM_EINVAL;
   if (bytes == 0) return TVLBM_OK;
   const int64_t n16 = bytes / 16;
-  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 8192);
+  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 65536);
   return launch_stream_copy(src, dst, n16, nblocks, (hipStream_t)stream) == hipSuccess ? TVLBM_OK
                                                                                      : TVLBM_EHIP;
 }
@@ -766,7 +766,7 @@ static int settle(tvlbm_ctx* c) {
   // a copy kernel, not a runtime copy: tvlbm_moments_static enqueues kernels
   // only (the buffers are multiples of 256 bytes: ld is a multiple of 64)
   const int64_t n16 = (int64_t)c->hl.q * c->plane * (int64_t)esize(c) / 16;
-  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 8192);
+  const int nblocks = (int)std::min<int64_t>(ceil_div(n16, 256), 65536);
   HIPCHK(c, launch_stream_copy(c->buf3, c->buf[c->cur ^ 1], n16, nblocks, c->st));
   c->pending = false;
   return TVLBM_OK;

@@ -43,3 +43,21 @@ def test_descriptor_layout_matches_header():
     assert d.ld.offset == 24 and d.tau.offset == 32 and d.collide.offset == 48
     assert d.wall_lo_ux.offset == 64 and d.dy.offset == 96 and d.stream.offset == 120
     assert ctypes.sizeof(d) == 128
+
+
+def test_stream_copy_rejects_bad_arguments():
+    """The copy helper's checks run on the host before anything is enqueued:
+    sizes that are not a multiple of 16 bytes, misaligned or null pointers."""
+    if not os.path.exists(tvlbm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(tvlbm.LIB_PATH)
+    f = lib.tvlbm_stream_copy
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    a, b = 0x10000, 0x20000  # never dereferenced: every call below fails its checks
+    assert f(a, b, 24, None) == tvlbm.TVLBM_EINVAL      # not a multiple of 16
+    assert f(a + 4, b, 32, None) == tvlbm.TVLBM_EINVAL  # misaligned source
+    assert f(a, b + 8, 32, None) == tvlbm.TVLBM_EINVAL  # misaligned destination
+    assert f(None, b, 32, None) == tvlbm.TVLBM_EINVAL
+    assert f(a, None, 32, None) == tvlbm.TVLBM_EINVAL
+    assert f(a, b, -16, None) == tvlbm.TVLBM_EINVAL
+    assert f(a, b, 0, None) == tvlbm.TVLBM_OK           # nothing to copy
