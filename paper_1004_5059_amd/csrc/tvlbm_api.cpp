@@ -107,6 +107,7 @@ struct tvlbm_ctx {
   void* d_inc = nullptr;
   double* d_dy = nullptr;
   int32_t* d_rowflag = nullptr;
+  int inc_rows = 0;     // longest list of rows crossing a wall (entries used in d_inc)
   std::vector<double> dyh;
   int dev = 0;          // device current at tvlbm_init
   // fixed-point deviation masses (2^-32 units) of the reference state [0]
@@ -152,6 +153,7 @@ bool build_row_tables(const HostLattice& H, const double* p, int ny, const doubl
   taps.assign((size_t)n * ny, TapD{});
   inc.assign(n, IncD{});
   flag.assign(ny, 0);
+  std::vector<int> used(ny, 1);  // longest tap list of each target row
   for (int b = 0; b < n; ++b) {
     const double s = (H.x[b] < 0 ? -1.0 : 1.0) * p[b];
     for (int k = 0; k < ny; ++k) {
@@ -169,6 +171,7 @@ bool build_row_tables(const HostLattice& H, const double* p, int ny, const doubl
         }
       }
       for (int t = cnt; t < 4; ++t) { T.src[t] = k; T.w[t] = 0.0; }
+      used[k] = std::max(used[k], cnt);
       T.glo = T.ghi = 0.0;
       if (walls) {
         if (s > 0.0) T.glo = ovl(-y[k], s - y[k], 0.0, dy[k]) / dy[k];
@@ -193,6 +196,9 @@ bool build_row_tables(const HostLattice& H, const double* p, int ny, const doubl
       for (int t = cnt; t < 4; ++t) { I.j[t] = 0; I.len[t] = 0.0; }
     }
   }
+  // the kernels read this many entries of every tap list of the row (the
+  // used ones come first; the rest have weight 0)
+  for (int k = 0; k < ny; ++k) flag[k] |= (used[k] - 1) << 2;
   return true;
 }
 
@@ -455,6 +461,7 @@ static int run_march(tvlbm_ctx* c, int mode, int aux, const void* src, void* dst
     A.inc = (const IncRows<R>*)c->d_inc;
     A.dy = c->d_dy;
     A.rowflag = c->d_rowflag;
+    A.inc_rows = c->inc_rows;
   }
   if (want_totals && g.nblocks > k.part_cap) return fail(c, TVLBM_EINVAL, "partials too small");
   HIPCHK(c, launch_march(c->hl.n, c->comp, mode, A, g.nblocks, c->st));
@@ -658,6 +665,11 @@ int tvlbm_init(const tvlbm_desc* d, tvlbm_ctx** out) {
       tvlbm_destroy(c);
       return TVLBM_EUNSUPPORTED;
     }
+    // the kernels read this many entries of every list (the used ones come
+    // first; the rest have length 0)
+    for (const IncD& I : inc)
+      for (int t = 0; t < 4; ++t)
+        if (I.len[t] > 0.0) c->inc_rows = std::max(c->inc_rows, t + 1);
     const int rc = c->f64 ? upload_rows<double>(c, taps, inc, flag) : upload_rows<float>(c, taps, inc, flag);
     if (rc != TVLBM_OK) {
       tvlbm_destroy(c);

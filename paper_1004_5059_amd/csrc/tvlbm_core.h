@@ -160,7 +160,9 @@ struct MarchArgs {
   const RowTap<R>* taps;  // non-uniform rows: [n][ny]
   const IncRows<R>* inc;  // non-uniform rows with walls: [n]
   const double* dy;       // non-uniform rows: [ny] heights
-  const int32_t* rowflag; // bit 0: row pulls the bottom ghost, bit 1: the top
+  const int32_t* rowflag; // bit 0: row pulls the bottom ghost, bit 1: the top;
+                          // bits 2-3: source rows read per tap list - 1
+  int32_t inc_rows;       // non-uniform rows with walls: entries used in inc[b] (max over b)
   unsigned long long* mass;  // CHECK / AUX_FIELDS: fixed-point deviation mass
                              // per instance (index Inst::id / work item), or null
 };

@@ -1087,36 +1087,71 @@ __global__ __launch_bounds__(256) void k_march2_batch(const MarchArgs<R> A) {
 }
 
 // ------------------------------------------------------- non-uniform rows --
-// Wall mass through a wall with non-uniform rows: the rows listed in inc[b]
-// carry the length len across the wall.
-template <typename R, int N>
-__device__ __forceinline__ R wall_mass_rows(const Lat<R>& L, const IncRows<R>* __restrict__ inc,
-                                            rsrc_t s, int64_t plane, uint32_t ld, int c, int nx,
-                                            int dir) {
-  const int cm = wrapc(c - 1, nx), cp = wrapc(c + 1, nx);
-  R m = R(0);
+// Wall masses through a wall with non-uniform rows, at two columns ca and cb:
+// the rows listed in I[b] carry the length len across the wall.  NT entries
+// are read for every b (the longest list; shorter ones end in zero lengths
+// on row 0, which add nothing), so that no load waits behind a branch.
+template <typename R, int N, int NT>
+__device__ __forceinline__ void wall_mass_rows(const Lat<R>& L, const IncRows<R> (&I)[N], rsrc_t s,
+                                               int64_t plane, uint32_t ld, int ca, int cb, int nx,
+                                               int dir, R& ma, R& mb) {
+  const int cam = wrapc(ca - 1, nx), cap = wrapc(ca + 1, nx);
+  const int cbm = wrapc(cb - 1, nx), cbp = wrapc(cb + 1, nx);
+  ma = R(0);
+  mb = R(0);
 #pragma unroll
   for (int b = 0; b < N; ++b) {
     if (node_sign<N>(b) != dir) continue;
-    const IncRows<R>& I = inc[b];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (I.len[t] == R(0)) continue;
-      const RowOff o = row_off((uint32_t)I.j[t] * ld, c, cm, cp);
-      R acc = R(0);
+    for (int t = 0; t < NT; ++t) {
+      const uint32_t rb = (uint32_t)I[b].j[t] * ld;
+      const RowOff oa = row_off(rb, ca, cam, cap), ob = row_off(rb, cb, cbm, cbp);
+      R acca = R(0), accb = R(0);
 #pragma unroll
-      for (int a = 0; a < N; ++a) acc += xpull<R, N>(L, s, (uint32_t)((a * N + b) * plane), a, o);
-      m = fmaR(I.len[t], acc, m);
+      for (int a = 0; a < N; ++a) {
+        const uint32_t pl = (uint32_t)((a * N + b) * plane);
+        acca += xpull<R, N>(L, s, pl, a, oa);
+        accb += xpull<R, N>(L, s, pl, a, ob);
+      }
+      ma = fmaR(I[b].len[t], acca, ma);
+      mb = fmaR(I[b].len[t], accb, mb);
     }
   }
-  return m;
+}
+
+// Wall mass through one wall (dir) at the lane's column ic and at its
+// neighbours im, ip.  Each lane forms the mass at its own column and the
+// neighbouring ones come from the adjacent lanes (consecutive columns; an
+// idle lane past the grid's last column holds column 0, its periodic
+// neighbour), except at the wavefront's two edge lanes, which form their
+// outer neighbour's mass themselves.  The arithmetic per column is the
+// same wherever it is formed.
+template <typename R, int N>
+__device__ __forceinline__ void wall_masses(const MarchArgs<R>& A, rsrc_t s, int64_t plane,
+                                            uint32_t ld, int ic, int im, int ip, int nx, int lane,
+                                            int dir, R& mc, R& mm, R& mp) {
+  IncRows<R> I[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+    if (node_sign<N>(b) == dir) I[b] = A.inc[b];
+  const int ce = lane == 0 ? im : (lane == 63 ? ip : ic);
+  R me;
+  switch (A.inc_rows) {
+    case 1: wall_mass_rows<R, N, 1>(A.lat, I, s, plane, ld, ic, ce, nx, dir, mc, me); break;
+    case 2: wall_mass_rows<R, N, 2>(A.lat, I, s, plane, ld, ic, ce, nx, dir, mc, me); break;
+    case 3: wall_mass_rows<R, N, 3>(A.lat, I, s, plane, ld, ic, ce, nx, dir, mc, me); break;
+    default: wall_mass_rows<R, N, 4>(A.lat, I, s, plane, ld, ic, ce, nx, dir, mc, me); break;
+  }
+  const R l = lane_from<DPP_PREV>(mc), r = lane_from<DPP_NEXT>(mc);
+  mm = lane == 0 ? me : l;
+  mp = lane == 63 ? me : r;
 }
 
 // One cell of a grid with tabulated (non-uniform) rows.
 template <typename R, int N, int ORD, bool COMP, int MODE>
 __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& P, rsrc_t s,
-                                          rsrc_t dst, int k, int i, bool active, double (&tot)[5],
-                                          int& bad) {
+                                          rsrc_t dst, int k, int i, int lane, bool active,
+                                          double (&tot)[5], int& bad) {
   constexpr int Q = N * N;
   const Lat<R>& L = A.lat;
   const int nx = P.nx, ny = P.ny;
@@ -1130,38 +1165,46 @@ __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& 
 #pragma unroll
     for (int l = 0; l < Q; ++l) d[l] = bld<R>(s, (uint32_t)k * ld + (uint32_t)ic, (uint32_t)(l * plane));
   } else {
+    // the row's tables are read once, up front, and the taps are loaded
+    // without a branch on their weights: the loads of a row are then issued
+    // together instead of one table read and one round trip per tap
     const int flag = A.rowflag[k];
+    RowTap<R> TT[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) TT[b] = A.taps[b * ny + k];
     R lo_c = R(0), lo_m = R(0), lo_p = R(0), hi_c = R(0), hi_m = R(0), hi_p = R(0);
-    if (flag & 1) {
-      lo_c = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ic, nx, -1);
-      lo_m = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, im, nx, -1);
-      lo_p = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ip, nx, -1);
-    }
-    if (flag & 2) {
-      hi_c = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ic, nx, +1);
-      hi_m = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, im, nx, +1);
-      hi_p = wall_mass_rows<R, N>(L, A.inc, s, plane, ld, ip, nx, +1);
-    }
+    if (flag & 1) wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, -1, lo_c, lo_m, lo_p);
+    if (flag & 2) wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, +1, hi_c, hi_m, hi_p);
+    // the first nt entries of every tap list of the row (nt: the longest
+    // list, the rest of a shorter one has weight 0 and adds nothing)
+    auto pull = [&](auto nt) {
+      constexpr int NT = decltype(nt)::value;
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const RowTap<R>& T = A.taps[b * ny + k];
-      RowOff o[4];
+      for (int b = 0; b < N; ++b) {
+        const RowTap<R>& T = TT[b];
+        RowOff o[NT];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) o[t] = row_off((uint32_t)T.src[t] * ld, ic, im, ip);
+        for (int t = 0; t < NT; ++t) o[t] = row_off((uint32_t)T.src[t] * ld, ic, im, ip);
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        const int l = a * N + b;
-        const uint32_t pl = (uint32_t)(l * plane);
-        R acc = R(0);
+        for (int a = 0; a < N; ++a) {
+          const int l = a * N + b;
+          const uint32_t pl = (uint32_t)(l * plane);
+          R acc = R(0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (T.w[t] != R(0)) acc = fmaR(T.w[t], xpull<R, N>(L, s, pl, a, o[t]), acc);
-        if ((flag & 1) && T.glo != R(0))
-          acc = fmaR(T.glo, ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], lo_c, lo_m, lo_p), acc);
-        if ((flag & 2) && T.ghi != R(0))
-          acc = fmaR(T.ghi, ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], hi_c, hi_m, hi_p), acc);
-        d[l] = acc;
+          for (int t = 0; t < NT; ++t) acc = fmaR(T.w[t], xpull<R, N>(L, s, pl, a, o[t]), acc);
+          if ((flag & 1) && T.glo != R(0))
+            acc = fmaR(T.glo, ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], lo_c, lo_m, lo_p), acc);
+          if ((flag & 2) && T.ghi != R(0))
+            acc = fmaR(T.ghi, ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], hi_c, hi_m, hi_p), acc);
+          d[l] = acc;
+        }
       }
+    };
+    switch ((flag >> 2) & 3) {
+      case 0:
+      case 1: pull(std::integral_constant<int, 2>{}); break;
+      case 2: pull(std::integral_constant<int, 3>{}); break;
+      default: pull(std::integral_constant<int, 4>{}); break;
     }
   }
   cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, k, i, active, A.dy[k], tot, bad);
@@ -1187,7 +1230,7 @@ __global__ __launch_bounds__(256) void k_rows(const MarchArgs<R> A) {
       const uint32_t bytes = (uint32_t)(Q * P.plane * (int64_t)sizeof(R));
       const rsrc_t s = make_rsrc(A.src + P.off, bytes);
       const rsrc_t dst = make_rsrc(A.dst + P.off, bytes);
-      rows_cell<R, N, ORD, COMP, MODE>(A, P, s, dst, k, i, i < P.nx, tot, bad);
+      rows_cell<R, N, ORD, COMP, MODE>(A, P, s, dst, k, i, lane, i < P.nx, tot, bad);
     }
   }
   if constexpr (MODE != MODE_STEP) {
