@@ -246,6 +246,35 @@ def test_refined_rows_parity(n, dtype, tol, walls):
                                atol=1e-10 * t0[0])
 
 
+# Rows of heights 1/4, 1/2 and 1 at both walls and in the bulk: target rows
+# pull from two, three or four source rows, and with displacements up to
+# 0.9 cell per axis (component CFL norm) four rows cross each wall per step
+# (three with the Euclidean norm, whose largest per-axis displacement is
+# 0.64): every length of tap and wall list the row-table step reads.
+MIXED_ROWS = np.array([0.25] * 4 + [0.5] * 2 + [1.0] * 6 + [0.5, 0.25, 0.25, 0.5] + [1.0] * 6
+                      + [0.5] * 2 + [0.25] * 4)
+
+
+@pytest.mark.parametrize("n,dtype,tol,cfl_norm", [(4, "f64", 1e-12, 1), (4, "f32", 1e-5, 1),
+                                                  (3, "f64", 1e-12, 1), (6, "f64", 1e-12, 0)])
+def test_refined_rows_long_lists_parity(n, dtype, tol, cfl_norm):
+    """Mixed row heights with walls, 60 steps, against the oracle."""
+    dy = MIXED_ROWS
+    ny, nx = len(dy), 40
+    s, g = make_pair(nx, ny, n=n, dtype=dtype, tau=0.7, dy=dy, walls=True, wall_lo=(0.0, 1.0),
+                     wall_hi=(0.05, 1.1), cfl_norm=cfl_norm)
+    fields = inputs.shear_wave_fields(nx, ny, eps=0.02)
+    noise = inputs.population_noise(n * n, ny, nx, amp=1e-4, seed=6)
+    s.set_fields(*fields, noise)
+    f_ref = g.set_fields(*fields, noise)
+    t0 = g.totals(f_ref)
+    s.step(60)
+    f_ref = g.run(f_ref, 60)
+    tot = _compare_state(s, g, f_ref, tol)
+    cons = 1e-13 if dtype == "f64" else 1e-6
+    assert abs(tot[0] - t0[0]) / t0[0] <= cons
+
+
 def test_refined_rows_uniform_heights_match_uniform_kernel():
     """Unit row heights through the row-table kernel reproduce the marching
     kernel (same arithmetic up to rounding order)."""
