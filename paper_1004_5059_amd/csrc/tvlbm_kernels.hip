@@ -1172,13 +1172,17 @@ __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& 
     RowTap<R> TT[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) TT[b] = A.taps[b * ny + k];
-    R lo_c = R(0), lo_m = R(0), lo_p = R(0), hi_c = R(0), hi_m = R(0), hi_p = R(0);
-    if (flag & 1) wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, -1, lo_c, lo_m, lo_p);
-    if (flag & 2) wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, +1, hi_c, hi_m, hi_p);
     // the first nt entries of every tap list of the row (nt: the longest
-    // list, the rest of a shorter one has weight 0 and adds nothing)
-    auto pull = [&](auto nt) {
-      constexpr int NT = decltype(nt)::value;
+    // list, the rest of a shorter one has weight 0 and adds nothing); the
+    // path is also specialised on the walls whose ghost the row pulls, so
+    // that a wall row's wall-mass and tap loads go out together
+    auto pull = [&](auto nt, auto wl) {
+      constexpr int NT = decltype(nt)::value, WL = decltype(wl)::value;
+      R lo_c = R(0), lo_m = R(0), lo_p = R(0), hi_c = R(0), hi_m = R(0), hi_p = R(0);
+      if constexpr ((WL & 1) != 0)
+        wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, -1, lo_c, lo_m, lo_p);
+      if constexpr ((WL & 2) != 0)
+        wall_masses<R, N>(A, s, plane, ld, ic, im, ip, nx, lane, +1, hi_c, hi_m, hi_p);
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         const RowTap<R>& T = TT[b];
@@ -1192,19 +1196,37 @@ __device__ __forceinline__ void rows_cell(const MarchArgs<R>& A, const Inst<R>& 
           R acc = R(0);
 #pragma unroll
           for (int t = 0; t < NT; ++t) acc = fmaR(T.w[t], xpull<R, N>(L, s, pl, a, o[t]), acc);
-          if ((flag & 1) && T.glo != R(0))
+          if ((WL & 1) && T.glo != R(0))
             acc = fmaR(T.glo, ghost_pull<R, N>(L, a, P.kap_lo[l], P.phi_lo[l], lo_c, lo_m, lo_p), acc);
-          if ((flag & 2) && T.ghi != R(0))
+          if ((WL & 2) && T.ghi != R(0))
             acc = fmaR(T.ghi, ghost_pull<R, N>(L, a, P.kap_hi[l], P.phi_hi[l], hi_c, hi_m, hi_p), acc);
           d[l] = acc;
         }
       }
     };
-    switch ((flag >> 2) & 3) {
-      case 0:
-      case 1: pull(std::integral_constant<int, 2>{}); break;
-      case 2: pull(std::integral_constant<int, 3>{}); break;
-      default: pull(std::integral_constant<int, 4>{}); break;
+    auto taps = [&](auto wl) {
+      switch ((flag >> 2) & 3) {
+        case 0:
+        case 1: pull(std::integral_constant<int, 2>{}, wl); break;
+        case 2: pull(std::integral_constant<int, 3>{}, wl); break;
+        default: pull(std::integral_constant<int, 4>{}, wl); break;
+      }
+    };
+    if constexpr (N > 4) {
+      // one wall path (both walls' masses; a row that does not pull a
+      // wall's ghost has zero weights for it): less code for the
+      // instruction cache
+      if (flag & 3)
+        taps(std::integral_constant<int, 3>{});
+      else
+        taps(std::integral_constant<int, 0>{});
+    } else {
+      switch (flag & 3) {
+        case 0: taps(std::integral_constant<int, 0>{}); break;
+        case 1: taps(std::integral_constant<int, 1>{}); break;
+        case 2: taps(std::integral_constant<int, 2>{}); break;
+        default: taps(std::integral_constant<int, 3>{}); break;
+      }
     }
   }
   cell_tail<R, N, ORD, COMP, MODE>(A, P, dst, d, k, i, active, A.dy[k], tot, bad);
