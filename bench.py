@@ -352,6 +352,34 @@ def run_c2(tol: float = 1e-8, k: int = 100):
             "kernel": "k_rows (non-uniform rows, diffuse walls)"}
 
 
+def run_c2_steps(steps: int, warmup: int = 200):
+    """The bounded-flow channel's step alone (512 x 288 refined rows, D2Q16
+    FP32, walls as in run_c2) from the uniform state: `warmup` steps, then
+    `steps` timed ones -- the row-table kernel under rocprofv3 counters
+    without the 256k-step solve."""
+    import torch
+
+    from paper_1004_5059_amd import inputs
+    from paper_1004_5059_amd.tvlbm import Solver
+
+    dy = inputs.refined_wall_rows(h=256, band=16, ratio=2)
+    ny = len(dy)
+    s = Solver(512, ny, n_gh=4, dtype="f32", tau=0.7, dy=dy, walls=True, wall_lo=(0.0, 1.0),
+               wall_hi=(0.05, 1.1), device="cuda:0")
+    s.set_fields(*inputs.uniform_fields(512, ny))
+    s.step(warmup)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(steps)
+    b.record(s.stream)
+    b.synchronize()
+    us = a.elapsed_time(b) * 1e3 / steps
+    s.close()
+    return {"grid": [512, ny], "steps": steps, "warmup": warmup, "us_per_step": round(us, 3),
+            "mlups": round(512 * ny / us, 1), "kernel": "k_rows (non-uniform rows, diffuse walls)"}
+
+
 def run_c4(n_train: int = 4096, n_test: int = 256, epochs: int = 40, batch: int = 32,
            lr: float = 2e-3, gen_start: str = "closed_form", tol: float = 1e-8):
     """Learned warm start: training states from batched steady solves of the
@@ -504,6 +532,9 @@ def main():
                          "(for counter runs)")
     ap.add_argument("--batched-load-only", action="store_true",
                     help="batched leg: full-load steps only, no steady solves")
+    ap.add_argument("--profile-rows", type=int, default=0,
+                    help="run only K steps of the bounded-flow channel (refined rows, after 200 "
+                         "warm-up steps), for counter runs under rocprofv3, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the TVLBM path here is single-GPU "
@@ -534,6 +565,10 @@ def main():
 
     if args.fv_only:
         print(json.dumps({"fv": fv_legs()}), flush=True)
+        return
+    if args.profile_rows > 0:
+        print(json.dumps({"profile_rows": leg("C2 steps", run_c2_steps, args.profile_rows)}),
+              flush=True)
         return
     if args.profile_variants:
         # each variant's k_march2 launches have their own grid size, which
