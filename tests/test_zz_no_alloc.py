@@ -68,8 +68,8 @@ def test_static_moments_flag_and_nulls():
 
 
 def test_static_moments_refuses_oversized_grid():
-    # 4100 x 1028 with non-uniform rows needs 65 x 257 = 16705 blocks of
-    # 4 rows x 64 columns; 1028 * 4 = 4112 rows need 66,822 > 65,536
+    # 4100 x 4112 with non-uniform rows needs ceil(4100 / 64) x (4112 / 4)
+    # = 65 x 1028 = 66,820 blocks of 64 columns x 4 rows, > 65,536
     nx, ny = 4100, 4112
     dy = np.full(ny, 1.0)
     dy[0] = 0.5
