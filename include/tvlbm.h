@@ -129,9 +129,9 @@ int tvlbm_moments(tvlbm_ctx *ctx, void *rho, void *ux, void *uy, void *T,
  * Outputs are caller-owned and valid once the stream reaches the call.
  * The per-block partial sums live in a static 2 MiB device array of the
  * library, one per GPU, resolved at tvlbm_init: grids needing more than
- * 65536 partial blocks (more than 16,777,216 cells with uniform rows,
- * 4,194,304 with non-uniform rows) are rejected with EINVAL before anything
- * is enqueued.  Calls that overlap on one GPU (several contexts or streams
+ * 65536 partial blocks (more than 67,108,864 cells with uniform rows, at
+ * 1024 cells per block; 16,777,216 with non-uniform rows, at 256) are
+ * rejected with EINVAL before anything is enqueued.  Calls that overlap on one GPU (several contexts or streams
  * at once) race on that array.  EINVAL also if the current device is not the
  * context's, or the populations are not set.  If the last launch was a
  * two-step one, the call first enqueues the step and the copy kernel that
